@@ -1,0 +1,318 @@
+"""FP64 CPU oracle for the NUFFT pair (paper Section 2.1, A = V F S and
+A^H = S^H F^H V^H), with coil handling (Section 2.2, multi-coil), the
+trajectory gradient and a plain conjugate-gradient driver.
+
+TEST INFRASTRUCTURE ONLY: only tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package.  It shares no code with the GPU
+library.  Inputs are the same float32 coordinates and complex64 images the GPU
+sees, widened exactly to float64 / complex128.
+
+Pins (all in tests/test_oracle_*.py, run on the CPU):
+  kb_ft ........ quadrature of kb_phi; kb_dphi ... central differences;
+  fftn ......... numpy.fft.fftn, Parseval;
+  forward ...... brute-force NUDFT, delta / constant image closed forms,
+                 Cartesian samples reduce to numpy.fft;
+  adjoint ...... <A x, y> = <x, A^H y> to 1e-12, single-sample closed form;
+  grad_points .. central finite differences of the oracle loss;
+  cg ........... CG on the explicit dense matrix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle_nufft.so")
+_lib = None
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_kb_beta.restype = ctypes.c_double
+    lib.orc_kb_beta.argtypes = [ctypes.c_int, ctypes.c_double]
+    for f in ("orc_i0", "orc_i1_over_z"):
+        getattr(lib, f).restype = ctypes.c_double
+        getattr(lib, f).argtypes = [ctypes.c_double]
+    for f in ("orc_kb_phi", "orc_kb_dphi", "orc_kb_ft"):
+        getattr(lib, f).restype = ctypes.c_double
+        getattr(lib, f).argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
+    lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_scaling.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _dp]
+    lib.orc_fftn.argtypes = [ctypes.c_int, _i64p, _dp, ctypes.c_int]
+    lib.orc_fft_axis.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, _dp, ctypes.c_int]
+    lib.orc_pad_scale.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _dp, _dp]
+    lib.orc_crop_scale.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _dp, _dp]
+    lib.orc_interp.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp]
+    lib.orc_grid.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp]
+    lib.orc_forward.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int64,
+                                _dp, _dp, _dp, _dp, _dp]
+    lib.orc_adjoint.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int64,
+                                _dp, _dp, _dp, _dp, _dp]
+    lib.orc_grad_points.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int64,
+                                    _dp, _dp, _dp, _dp]
+    _lib = lib
+    return lib
+
+
+def _shape(v):
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.int64))
+    return a, a.ctypes.data_as(_i64p)
+
+
+def _c128(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    return a, a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a, a.ctypes.data_as(_dp)
+
+
+def _null():
+    return ctypes.cast(None, _dp)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+# ------------------------------------------------------------------ kernel
+def kb_beta(J: int, sigma: float) -> float:
+    return float(_load().orc_kb_beta(int(J), float(sigma)))
+
+
+def i0(z: float) -> float:
+    return float(_load().orc_i0(float(z)))
+
+
+def i1_over_z(z: float) -> float:
+    return float(_load().orc_i1_over_z(float(z)))
+
+
+def kb_phi(t: float, J: int, beta: float) -> float:
+    return float(_load().orc_kb_phi(float(t), int(J), float(beta)))
+
+
+def kb_dphi(t: float, J: int, beta: float) -> float:
+    return float(_load().orc_kb_dphi(float(t), int(J), float(beta)))
+
+
+def kb_ft(xi: float, J: int, beta: float) -> float:
+    return float(_load().orc_kb_ft(float(xi), int(J), float(beta)))
+
+
+def scaling(N, K, J) -> list:
+    """Per-axis scaling tables s_a(i) = 1/Phi_a((i - N_a/2)/K_a)."""
+    N = list(N)
+    out = np.empty(sum(N), dtype=np.float64)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    _load().orc_scaling(len(N), np_, kp, int(J), out.ctypes.data_as(_dp))
+    res, off = [], 0
+    for n_a in N:
+        res.append(out[off:off + n_a].copy())
+        off += n_a
+    return res
+
+
+# ------------------------------------------------------------------ FFT
+def fftn(a, sign: int = -1) -> np.ndarray:
+    """Unnormalised multi-dimensional DFT with kernel e^{sign 2 pi i q k / L}."""
+    arr, p = _c128(np.array(a, dtype=np.complex128, copy=True))
+    s, sp = _shape(arr.shape)
+    _load().orc_fftn(arr.ndim, sp, p, int(sign))
+    return arr
+
+
+def fft_axis(a, axis: int, sign: int = -1) -> np.ndarray:
+    arr, p = _c128(np.array(a, dtype=np.complex128, copy=True))
+    s, sp = _shape(arr.shape)
+    _load().orc_fft_axis(arr.ndim, sp, int(axis), p, int(sign))
+    return arr
+
+
+# ------------------------------------------------------------------ stages
+def pad_scale(x, N, K, J) -> np.ndarray:
+    d = len(N)
+    xx, xp = _c128(x)
+    g = np.empty(tuple(K), dtype=np.complex128)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    _load().orc_pad_scale(d, np_, kp, int(J), xp, g.ctypes.data_as(_dp))
+    return g
+
+
+def crop_scale(H, N, K, J) -> np.ndarray:
+    d = len(N)
+    hh, hp = _c128(H)
+    x = np.empty(tuple(N), dtype=np.complex128)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    _load().orc_crop_scale(d, np_, kp, int(J), hp, x.ctypes.data_as(_dp))
+    return x
+
+
+def interp(G, om, N, K, J) -> np.ndarray:
+    d = len(N)
+    om_, omp = _f64(om)
+    M = om_.shape[0]
+    gg, gp = _c128(G)
+    y = np.empty(M, dtype=np.complex128)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    _load().orc_interp(d, np_, kp, int(J), M, omp, gp, y.ctypes.data_as(_dp))
+    return y
+
+
+def grid(y, om, N, K, J) -> np.ndarray:
+    d = len(N)
+    om_, omp = _f64(om)
+    M = om_.shape[0]
+    yy, yp = _c128(y)
+    h = np.empty(tuple(K), dtype=np.complex128)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    _load().orc_grid(d, np_, kp, int(J), M, omp, yp, h.ctypes.data_as(_dp))
+    return h
+
+
+# ------------------------------------------------------------------ transforms
+def forward(x, om, N, K, J, stages: bool = False):
+    """y = V F S x.  With stages=True also returns (g, G): the padded scaled
+    image and its oversampled FFT."""
+    d = len(N)
+    om_, omp = _f64(om)
+    M = om_.shape[0]
+    xx, xp = _c128(np.asarray(x).reshape(tuple(N)))
+    y = np.empty(M, dtype=np.complex128)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    if stages:
+        g = np.empty(tuple(K), dtype=np.complex128)
+        G = np.empty(tuple(K), dtype=np.complex128)
+        _load().orc_forward(d, np_, kp, int(J), M, omp, xp, y.ctypes.data_as(_dp),
+                            g.ctypes.data_as(_dp), G.ctypes.data_as(_dp))
+        return y, g, G
+    _load().orc_forward(d, np_, kp, int(J), M, omp, xp, y.ctypes.data_as(_dp), _null(), _null())
+    return y
+
+
+def adjoint(y, om, N, K, J, stages: bool = False):
+    """x = S^H F^H V^H y.  With stages=True also returns (h, H): the gridded
+    samples and their inverse oversampled FFT."""
+    d = len(N)
+    om_, omp = _f64(om)
+    M = om_.shape[0]
+    yy, yp = _c128(y)
+    x = np.empty(tuple(N), dtype=np.complex128)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    if stages:
+        h = np.empty(tuple(K), dtype=np.complex128)
+        H = np.empty(tuple(K), dtype=np.complex128)
+        _load().orc_adjoint(d, np_, kp, int(J), M, omp, yp, x.ctypes.data_as(_dp),
+                            h.ctypes.data_as(_dp), H.ctypes.data_as(_dp))
+        return x, h, H
+    _load().orc_adjoint(d, np_, kp, int(J), M, omp, yp, x.ctypes.data_as(_dp), _null(), _null())
+    return x
+
+
+def forward_grid(x, N, K, J) -> np.ndarray:
+    """G = F S x (the oversampled spectrum the interpolator reads)."""
+    return fftn(pad_scale(x, N, K, J), -1)
+
+
+def grad_points(G, gy, om, N, K, J, out=None) -> np.ndarray:
+    """Trajectory gradient of a real loss through y = V(omega) G, given the
+    torch-convention gradient gy of y.  Adds into `out` when given."""
+    d = len(N)
+    om_, omp = _f64(om)
+    M = om_.shape[0]
+    gg, gp = _c128(G)
+    yy, yp = _c128(gy)
+    if out is None:
+        out = np.zeros((M, d), dtype=np.float64)
+    o = np.ascontiguousarray(out, dtype=np.float64)
+    n, np_ = _shape(N)
+    k, kp = _shape(K)
+    _load().orc_grad_points(d, np_, kp, int(J), M, omp, gp, yp, o.ctypes.data_as(_dp))
+    return o
+
+
+# ------------------------------------------------------------------ coils (Section 2.2)
+def forward_coils(x, coils, om, N, K, J) -> np.ndarray:
+    """y_i = A (c_i * x) for every coil i."""
+    return np.stack([forward(np.asarray(c, np.complex128) * np.asarray(x, np.complex128),
+                             om, N, K, J) for c in coils])
+
+
+def adjoint_coils(ys, coils, om, N, K, J) -> np.ndarray:
+    """sum_i conj(c_i) * A^H y_i."""
+    acc = np.zeros(tuple(N), dtype=np.complex128)
+    for c, y in zip(coils, ys):
+        acc += np.conj(np.asarray(c, np.complex128)) * adjoint(y, om, N, K, J)
+    return acc
+
+
+def loss_and_grads(x, om, coils, target_y, N, K, J):
+    """L = sum_i ||A(c_i x) - y_i||^2 with its torch-convention image gradient
+    2 sum_i conj(c_i) A^H r_i and the trajectory gradient (float64 [M, d])."""
+    x = np.asarray(x, np.complex128)
+    M = np.asarray(om).shape[0]
+    L = 0.0
+    gx = np.zeros(tuple(N), np.complex128)
+    gom = np.zeros((M, len(N)), np.float64)
+    for c, yt in zip(coils, target_y):
+        cx = np.asarray(c, np.complex128) * x
+        G = forward_grid(cx, N, K, J)
+        y = interp(G, om, N, K, J)
+        r = y - np.asarray(yt, np.complex128)
+        L += float(np.vdot(r, r).real)
+        gy = 2.0 * r
+        gx += np.conj(np.asarray(c, np.complex128)) * adjoint(gy, om, N, K, J)
+        grad_points(G, gy, om, N, K, J, out=gom)
+    return L, gx, gom
+
+
+# ------------------------------------------------------------------ CG
+def cg(apply_normal, b, iters: int):
+    """Conjugate gradient on the Hermitian positive semi-definite system
+    N x = b, x0 = 0, <a, b> = sum conj(a) b, a fixed number of iterations,
+    no preconditioner, no restart.  Returns (x, residual norms per iteration)."""
+    b = np.asarray(b, np.complex128)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(np.vdot(r, r).real)
+    hist = [np.sqrt(rr)]
+    for _ in range(iters):
+        Ap = apply_normal(p)
+        pAp = float(np.vdot(p, Ap).real)
+        if pAp == 0.0:
+            break
+        alpha = rr / pAp
+        x = x + alpha * p
+        r = r - alpha * Ap
+        rr_new = float(np.vdot(r, r).real)
+        hist.append(np.sqrt(rr_new))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x, np.array(hist)
+
+
+def cg_nufft(y, om, N, K, J, iters: int = 30):
+    """CG on A^H A x = A^H y with the oracle pair."""
+    b = adjoint(y, om, N, K, J)
+    return cg(lambda p: adjoint(forward(p, om, N, K, J), om, N, K, J), b, iters)
