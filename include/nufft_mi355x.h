@@ -1,0 +1,160 @@
+/*
+ * nufft_mi355x: the NUFFT pair A = V F S and A^H = S^H F^H V^H on one MI355X
+ * (gfx950) GPU.
+ *
+ * The operator follows the paper (PyNUFFT, arXiv 1710.03197):
+ *   Section 2.1, Eq. A = VFS: scaling S, oversampled FFT F (zero padding from
+ *     N to K per axis), interpolation V onto M non-Cartesian samples;
+ *   Section 2.1 "Adjoint PyNUFFT", Eq. A^H = S^H F^H V^H: gridding V^H, inverse
+ *     oversampled FFT with crop, rescaling;
+ *   Section 2.1, batch mode ("serial or parallel processing");
+ *   Section 2.2 "Multi-coil regularized image reconstruction": coil maps c_i
+ *     multiply before A and, conjugated, after A^H.
+ *
+ * Conventions.  Arrays are C order (last axis fastest).  Image index i_a in
+ * [0, N_a) stands for n_a = i_a - N_a/2.  The forward kernel is e^{-i omega.n}
+ * (y_m ~ sum_n x_n e^{-i omega_m . n}); FFTs are unnormalised both ways, so the
+ * adjoint is the exact conjugate transpose of the forward (no 1/K^d factor).
+ * The interpolator is a separable Kaiser-Bessel kernel of J taps per axis with
+ * Beatty's shape beta_a = pi sqrt((J/s_a)^2 (s_a - 1/2)^2 - 0.8), s_a = K_a/N_a;
+ * the scaling is the reciprocal of its continuous Fourier transform.  The
+ * window of sample m on axis a is the J integers in (u - J/2, u + J/2],
+ * u = omega_{m,a} * (K_a / (2 pi)) evaluated as one float64 multiply; taps wrap
+ * modulo K_a, so any finite omega is accepted (periodic).
+ *
+ * Data types: images and samples are complex64 (interleaved float re, im);
+ * trajectories are float32 [M][d] in radians.  Arithmetic is float32 with
+ * float32 accumulation; window positions are float64.
+ *
+ * Memory: every pointer argument named *_dev is device memory that the caller
+ * owns; the library never frees or retains it beyond the call (nufft_plan and
+ * nufft_set_points copy the trajectory).  A plan owns its workspace.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Transform
+ * calls are asynchronous on that stream and allocate nothing once the plan's
+ * workspace is large enough for the batch (see nufft_reserve), so they may be
+ * captured into a hipGraph.  Plan creation and nufft_set_points synchronise.
+ *
+ * Concurrency: a plan owns one workspace, so at most one call per plan may be
+ * in flight; distinct plans are independent.
+ *
+ * Errors: every entry point returns a nufft_status (0 = success, negative =
+ * failure) and never throws or aborts.  nufft_last_error() returns a
+ * thread-local description of the most recent failure on the calling thread.
+ */
+#ifndef NUFFT_MI355X_H
+#define NUFFT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NUFFT_OK = 0,
+    NUFFT_ERR_INVALID_ARG = -1, /* a size, pointer or count is out of range */
+    NUFFT_ERR_NO_DEVICE = -2,   /* no HIP device is visible */
+    NUFFT_ERR_OOM = -3,         /* a device allocation failed */
+    NUFFT_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed */
+    NUFFT_ERR_BAD_PLAN = -5,    /* NULL, destroyed or foreign plan handle */
+    NUFFT_ERR_NONFINITE = -6,   /* a trajectory coordinate is NaN or infinite */
+    NUFFT_ERR_UNSUPPORTED = -7  /* valid request the library does not handle */
+} nufft_status;
+
+typedef struct nufft_plan_s *nufft_plan_t;
+
+/* Create a plan for the d-dimensional pair (Section 2.1, Eq. A = VFS).
+ *   d      : 1, 2 or 3.
+ *   N[d]   : image size per axis, even, >= 2.
+ *   K[d]   : oversampled grid size per axis, even, K_a >= N_a, K_a <= 8192,
+ *            and K_a has no prime factor above 5 (mixed-radix 2/3/4/5/8 FFT).
+ *   J      : taps per axis, 2 <= J <= 16 and J <= K_a.
+ *   M      : number of samples, 0 <= M < 2^31.
+ *   om_dev : device float32 [M][d], radians; copied into the plan.  May be
+ *            NULL when M == 0.
+ *   stream : stream used for the plan-time kernels; the call synchronises it.
+ *   out    : receives the handle.
+ * Errors: INVALID_ARG, NO_DEVICE, OOM, HIP, NONFINITE (no plan is returned). */
+int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
+               const float *om_dev, void *stream, nufft_plan_t *out);
+
+/* Replace the trajectory (same M) and re-bin it; synchronises `stream`.
+ * On NONFINITE the plan keeps its previous trajectory. */
+int nufft_set_points(nufft_plan_t plan, const float *om_dev, void *stream);
+
+/* Coil mode (Section 2.2, multi-coil): with C >= 1 maps c_dev = complex64
+ * [C][N^d] (copied into the plan), the forward maps one image x to C sample
+ * vectors y_i = A (c_i * x), stored [C][M], and the adjoint maps [C][M] to one
+ * image sum_i conj(c_i) * A^H y_i.  C = 0 (c_dev NULL) returns to single mode.
+ * Synchronous. */
+int nufft_set_coils(nufft_plan_t plan, int C, const void *c_dev);
+
+/* Grow the plan's workspace for batches of up to B images (B * C grids).  The
+ * batched calls grow it on demand; calling this first keeps them
+ * allocation-free. */
+int nufft_reserve(nufft_plan_t plan, int B);
+
+/* y = A x (Section 2.1, Eq. A = VFS).  x_dev complex64 [N^d]; y_dev complex64
+ * [M] ([C][M] in coil mode), in the caller's sample order.  x and y must not
+ * overlap.  Asynchronous on `stream`. */
+int nufft_forward(nufft_plan_t plan, const void *x_dev, void *y_dev, void *stream);
+
+/* x = A^H y (Section 2.1, Eq. A^H = S^H F^H V^H): x_n ~ sum_m y_m e^{+i omega_m.n}.
+ * y_dev complex64 [M] ([C][M] in coil mode); x_dev complex64 [N^d]. */
+int nufft_adjoint(nufft_plan_t plan, const void *y_dev, void *x_dev, void *stream);
+
+/* B independent transforms sharing the trajectory (Section 2.1, batch mode):
+ * x [B][N^d] -> y [B][M] ([B][C][M] in coil mode), and back. */
+int nufft_forward_batched(nufft_plan_t plan, int B, const void *x_dev, void *y_dev, void *stream);
+int nufft_adjoint_batched(nufft_plan_t plan, int B, const void *y_dev, void *x_dev, void *stream);
+
+/* Trajectory gradient of a real loss L through y = A(omega) x (torch
+ * convention): given gy_dev = dL/dRe y + i dL/dIm y, complex64 [M] ([C][M] in
+ * coil mode), writes gom_dev float32 [M][d] with
+ *   gom[m][a] = sum_i Re( conj(gy_i[m]) * dy_i[m]/domega_{m,a} ),
+ * the derivative taken through the interpolation weights (derivative of the
+ * Kaiser-Bessel kernel) of the same approximate operator.  x_dev is the image
+ * the forward was applied to.  Uses the plan's workspace for F S (c_i x). */
+int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev,
+                      float *gom_dev, void *stream);
+
+/* Stage entry points, for stage-wise checks.  The K^d grid is complex64 in C
+ * order (no batching, no coils):
+ *   nufft_stage_fs   : G = F S x   (scaling, zero padding, oversampled FFT)
+ *   nufft_stage_v    : y = V G     (interpolation only)
+ *   nufft_stage_vh   : h = V^H y   (gridding only; h is fully overwritten)
+ *   nufft_stage_shfh : x = S^H F^H h (inverse FFT, crop, rescaling) */
+int nufft_stage_fs(nufft_plan_t plan, const void *x_dev, void *G_dev, void *stream);
+int nufft_stage_v(nufft_plan_t plan, const void *G_dev, void *y_dev, void *stream);
+int nufft_stage_vh(nufft_plan_t plan, const void *y_dev, void *h_dev, void *stream);
+int nufft_stage_shfh(nufft_plan_t plan, const void *h_dev, void *x_dev, void *stream);
+
+/* Plan facts: beta per axis, the kernel's polynomial degree, tile shape,
+ * number of bins / scatter work items, workspace bytes.  Any pointer may be
+ * NULL.  Host only. */
+int nufft_plan_info(nufft_plan_t plan, double *beta3, int *poly_degree, int *tile3,
+                    int64_t *n_bins, int64_t *n_items, int64_t *workspace_bytes);
+
+/* Kernel weights the GPU evaluates, computed on the host from the same
+ * plan-time polynomial fit (float32 coefficients, float32 Horner): for
+ * fractional offsets f[i] in [0, 1) writes w[i*J + j] = phi(f + J/2 - 1 - j),
+ * phi(t) = I0(beta sqrt(1 - (2t/J)^2)) with beta from (J, sigma), and
+ * dw[i*J + j] = phi'(f + J/2 - 1 - j) (dw may be NULL).  Needs no device. */
+int nufft_kernel_weights_host(int J, double sigma, int64_t n, const double *f, double *w, double *dw);
+
+/* Synchronise the plan's last stream and free everything.  A NULL, destroyed
+ * or foreign handle returns BAD_PLAN and is not touched. */
+int nufft_destroy(nufft_plan_t plan);
+
+const char *nufft_status_string(int status);
+const char *nufft_last_error(void);
+
+/* Number of visible HIP devices (0 when none); needs no plan. */
+int nufft_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUFFT_MI355X_H */

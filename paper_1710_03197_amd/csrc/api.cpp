@@ -1,0 +1,816 @@
+// C ABI of libnufft_mi355x: plan lifetime, validation, binning, work-item
+// construction and the stage sequences of the NUFFT pair
+//   forward  y = V F S x        (paper Section 2.1, Eq. A = VFS)
+//   adjoint  x = S^H F^H V^H y  (Section 2.1 "Adjoint PyNUFFT")
+// with batch mode (Section 2.1) and coil maps (Section 2.2, multi-coil).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/nufft_mi355x.h"
+#include "nufft_internal.h"
+
+using namespace nufft;
+
+namespace {
+
+constexpr uint64_t kMagic = 0x4e55464654333535ull;  // "NUFFT355"
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_last_error;
+std::mutex g_registry_mu;
+std::set<const void *> g_registry;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(NUFFT_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
+    return fail(NUFFT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+template <class T>
+hipError_t dmalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+template <class T>
+void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <class T>
+hipError_t upload(T **p, const std::vector<T> &v) {
+    hipError_t e = dmalloc(p, v.size());
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+bool smooth235(int64_t k) {
+    for (int p : {2, 3, 5})
+        while (k % p == 0) k /= p;
+    return k == 1;
+}
+
+}  // namespace
+
+struct nufft_plan_s {
+    uint64_t magic = kMagic;
+    int device = 0;
+    int d = 0;
+    int64_t N[kMaxDim] = {1, 1, 1};
+    int64_t K[kMaxDim] = {1, 1, 1};
+    int J = 0;
+    int64_t M = 0;
+    AxisKernel ker[kMaxDim];
+    RadixPlan rp[kMaxDim];
+    int T[kMaxDim] = {1, 1, 1};
+    int nt[kMaxDim] = {1, 1, 1};
+    int R[kMaxDim] = {1, 1, 1};
+    int tile_cells = 1;
+    int64_t nbins = 1;
+    int chunk = 2048;
+    int64_t img_elems = 1, grid_elems = 1, tmp_elems = 1;
+
+    // device constants
+    float *scale[kMaxDim] = {nullptr, nullptr, nullptr};
+    float2 *tw[kMaxDim] = {nullptr, nullptr, nullptr};
+    float *coef[kMaxDim] = {nullptr, nullptr, nullptr};
+    float *dcoef[kMaxDim] = {nullptr, nullptr, nullptr};
+    // trajectory and binning
+    float *om = nullptr;
+    float *om_sorted = nullptr;
+    int *perm = nullptr;
+    int *bin_start = nullptr;
+    GridItem *items = nullptr;
+    int64_t n_items = 0;
+    HotTile *hot = nullptr;
+    int64_t n_hot = 0;
+    int64_t n_slots = 0;
+    // coils
+    float2 *coils = nullptr;
+    int C = 1;
+    bool coil_mode = false;
+    // workspace
+    int cap_grids = 0;
+    int64_t cap_slots = -1;
+    float2 *grid = nullptr;
+    float2 *tmp = nullptr;
+    float2 *partials = nullptr;
+    hipStream_t last_stream = nullptr;
+
+    SampleGeom geom() const {
+        SampleGeom g{};
+        g.d = d;
+        g.J = J;
+        for (int a = 0; a < d; ++a) {
+            g.K[a] = int(K[a]);
+            g.C[a] = double(K[a]) / (2.0 * kPi);
+            g.deg[a] = ker[a].deg;
+            g.deg_d[a] = ker[a].deg_d;
+            g.coef[a] = coef[a];
+            g.dcoef[a] = dcoef[a];
+        }
+        return g;
+    }
+};
+
+namespace {
+
+int check_plan(nufft_plan_t p) {
+    if (!p) return fail(NUFFT_ERR_BAD_PLAN, "plan handle is NULL");
+    std::lock_guard<std::mutex> lk(g_registry_mu);
+    if (!g_registry.count(p)) return fail(NUFFT_ERR_BAD_PLAN, "plan handle is not a live plan");
+    if (p->magic != kMagic) return fail(NUFFT_ERR_BAD_PLAN, "plan handle is corrupted");
+    return NUFFT_OK;
+}
+
+void free_plan(nufft_plan_s *p) {
+    for (int a = 0; a < kMaxDim; ++a) {
+        dfree(p->scale[a]);
+        dfree(p->tw[a]);
+        dfree(p->coef[a]);
+        dfree(p->dcoef[a]);
+    }
+    dfree(p->om);
+    dfree(p->om_sorted);
+    dfree(p->perm);
+    dfree(p->bin_start);
+    dfree(p->items);
+    dfree(p->hot);
+    dfree(p->coils);
+    dfree(p->grid);
+    dfree(p->tmp);
+    dfree(p->partials);
+}
+
+// Tile edge on one axis: the largest divisor of K that is <= target, raised
+// to the smallest divisor >= need when it would be smaller (so a window of
+// J taps reaches at most three tiles per axis).
+int choose_tile(int64_t K, int target, int need) {
+    int best = 1;
+    for (int64_t t = 1; t <= K && t <= target; ++t)
+        if (K % t == 0) best = int(t);
+    if (best < need) {
+        for (int64_t t = need; t <= K; ++t)
+            if (K % t == 0) return int(t);
+        return int(K);
+    }
+    return best;
+}
+
+int bits_for(int64_t n) {
+    int b = 1;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+// Bin the trajectory om (device, caller order) into the plan: sorted copy,
+// permutation, bin offsets, scatter work items.  Synchronous.
+int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
+    const int64_t M = p->M;
+    const int d = p->d;
+    if (M > 0) HIP_TRY(hipMemcpyAsync(p->om, om_dev, size_t(M) * d * sizeof(float), hipMemcpyDeviceToDevice, s),
+                       "copy trajectory");
+    int *keys = nullptr, *keys_sorted = nullptr, *iota = nullptr, *counts = nullptr, *flag = nullptr;
+    auto cleanup = [&]() {
+        dfree(keys);
+        dfree(keys_sorted);
+        dfree(iota);
+        dfree(counts);
+        dfree(flag);
+    };
+    std::vector<int> hcounts(size_t(p->nbins), 0);
+    int hflag = 0;
+    hipError_t e = hipSuccess;
+    do {
+        if ((e = dmalloc(&keys, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
+        if ((e = dmalloc(&keys_sorted, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
+        if ((e = dmalloc(&iota, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
+        if ((e = dmalloc(&counts, size_t(p->nbins))) != hipSuccess) break;
+        if ((e = dmalloc(&flag, 1)) != hipSuccess) break;
+        if ((e = hipMemsetAsync(counts, 0, size_t(p->nbins) * sizeof(int), s)) != hipSuccess) break;
+        if ((e = hipMemsetAsync(flag, 0, sizeof(int), s)) != hipSuccess) break;
+        BinArgs ba{};
+        ba.om = p->om;
+        ba.M = M;
+        ba.d = d;
+        ba.J = p->J;
+        for (int a = 0; a < d; ++a) {
+            ba.K[a] = int(p->K[a]);
+            ba.C[a] = double(p->K[a]) / (2.0 * kPi);
+            ba.T[a] = p->T[a];
+            ba.nt[a] = p->nt[a];
+        }
+        ba.keys = keys;
+        ba.counts = counts;
+        ba.flag = flag;
+        if ((e = launch_bin_keys(ba, s)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(hcounts.data(), counts, size_t(p->nbins) * sizeof(int), hipMemcpyDeviceToHost,
+                                s)) != hipSuccess)
+            break;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+        if (hflag) break;
+        if ((e = launch_iota(iota, M, s)) != hipSuccess) break;
+        if ((e = sort_pairs(keys, keys_sorted, iota, p->perm, M, bits_for(p->nbins), s)) != hipSuccess) break;
+        if ((e = launch_permute_points(p->om, p->perm, M, d, p->om_sorted, s)) != hipSuccess) break;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    } while (false);
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, "binning the trajectory");
+    if (hflag) return fail(NUFFT_ERR_NONFINITE, "trajectory has a NaN, infinite or out-of-range coordinate");
+
+    // bin offsets
+    std::vector<int> start(size_t(p->nbins) + 1, 0);
+    for (int64_t b = 0; b < p->nbins; ++b) start[b + 1] = start[b] + hcounts[b];
+    // scatter work items: per tile, the samples of the distinct bins whose
+    // windows can reach it, split into chunks
+    std::vector<GridItem> items;
+    std::vector<HotTile> hot;
+    int64_t slots = 0;
+    items.reserve(size_t(p->nbins));
+    for (int64_t t = 0; t < p->nbins; ++t) {
+        int tc[kMaxDim];
+        int64_t rem = t;
+        for (int a = d - 1; a >= 0; --a) {
+            tc[a] = int(rem % p->nt[a]);
+            rem /= p->nt[a];
+        }
+        int64_t S = 0;
+        int r[kMaxDim] = {0, 0, 0};
+        while (true) {
+            int64_t bin = 0;
+            for (int a = 0; a < d; ++a) {
+                int bt = tc[a] - r[a];
+                if (bt < 0) bt += p->nt[a];
+                bin = bin * p->nt[a] + bt;
+            }
+            S += hcounts[bin];
+            int a = d - 1;
+            while (a >= 0) {
+                if (++r[a] < p->R[a]) break;
+                r[a] = 0;
+                --a;
+            }
+            if (a < 0) break;
+        }
+        const int nch = int(std::max<int64_t>(1, (S + p->chunk - 1) / p->chunk));
+        const int slot = nch > 1 ? int(slots) : -1;
+        for (int c = 0; c < nch; ++c) items.push_back(GridItem{int(t), c, nch, slot});
+        if (nch > 1) {
+            hot.push_back(HotTile{int(t), slot, nch, 0});
+            slots += nch;
+        }
+    }
+    dfree(p->bin_start);
+    dfree(p->items);
+    dfree(p->hot);
+    HIP_TRY(upload(&p->bin_start, start), "upload bin offsets");
+    HIP_TRY(upload(&p->items, items), "upload work items");
+    HIP_TRY(upload(&p->hot, hot), "upload hot tiles");
+    p->n_items = int64_t(items.size());
+    p->n_hot = int64_t(hot.size());
+    p->n_slots = slots;
+    return NUFFT_OK;
+}
+
+// Workspace for `grids` simultaneous K^d grids.
+int ensure_workspace(nufft_plan_s *p, int grids) {
+    if (grids <= p->cap_grids && p->n_slots <= p->cap_slots) return NUFFT_OK;
+    const int g = std::max(grids, p->cap_grids);
+    if (g > p->cap_grids) {
+        dfree(p->grid);
+        dfree(p->tmp);
+        p->cap_grids = 0;
+        HIP_TRY(dmalloc(&p->grid, size_t(g) * p->grid_elems), "allocate grid workspace");
+        HIP_TRY(dmalloc(&p->tmp, size_t(g) * std::max<int64_t>(p->tmp_elems, 1)), "allocate pass workspace");
+    }
+    dfree(p->partials);
+    p->cap_slots = -1;
+    HIP_TRY(dmalloc(&p->partials, size_t(g) * std::max<int64_t>(p->n_slots, 1) * p->tile_cells),
+            "allocate partial tiles");
+    p->cap_grids = g;
+    p->cap_slots = p->n_slots;
+    return NUFFT_OK;
+}
+
+// ---- stage sequences
+
+// G = F S (c x): x [B][N^d] -> out [B*C][K^d]; intermediates in the workspace.
+int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) {
+    const int d = p->d;
+    const int C = p->coil_mode ? p->C : 1;
+    const int64_t grids = int64_t(B) * C;
+    const float2 *cur = x;
+    for (int pass = 0; pass < d; ++pass) {
+        const int ax = d - 1 - pass;
+        float2 *dst = (pass == d - 1) ? out : (((d - 1 - pass) % 2 == 0) ? p->grid : p->tmp);
+        if (pass == 0) {
+            FirstPassArgs a{};
+            a.x = cur;
+            a.out = dst;
+            a.tw = p->tw[ax];
+            a.rp = p->rp[ax];
+            a.coils = p->coil_mode ? p->coils : nullptr;
+            a.C = C;
+            a.B = B;
+            a.K = int(p->K[ax]);
+            a.N = int(p->N[ax]);
+            a.rows = 1;
+            for (int b = 0; b < d - 1; ++b) a.rows *= p->N[b];
+            a.d = d;
+            for (int b = 0; b < d; ++b) {
+                a.Nax[b] = int(p->N[b]);
+                a.scale[b] = p->scale[b];
+            }
+            HIP_TRY(launch_first_pass(a, s), "forward first FFT pass");
+        } else {
+            StridedPassArgs a{};
+            a.in = cur;
+            a.out = dst;
+            a.tw = p->tw[ax];
+            a.rp = p->rp[ax];
+            a.K = int(p->K[ax]);
+            a.Lin = int(p->N[ax]);
+            a.Lout = int(p->K[ax]);
+            a.outer = 1;
+            for (int b = 0; b < ax; ++b) a.outer *= p->N[b];
+            a.inner = 1;
+            for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
+            a.grids = grids;
+            a.inverse = false;
+            HIP_TRY(launch_strided_pass(a, s), "forward strided FFT pass");
+        }
+        cur = dst;
+    }
+    return NUFFT_OK;
+}
+
+// x = S^H F^H h (coil-combined): h [B*C][K^d] -> x [B][N^d].
+int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s) {
+    const int d = p->d;
+    const int C = p->coil_mode ? p->C : 1;
+    const int64_t grids = int64_t(B) * C;
+    const float2 *cur = h;
+    for (int ax = 0; ax < d; ++ax) {
+        if (ax == d - 1) {
+            LastPassArgs a{};
+            a.in = cur;
+            a.x = x;
+            a.tw = p->tw[ax];
+            a.rp = p->rp[ax];
+            a.coils = p->coil_mode ? p->coils : nullptr;
+            a.C = C;
+            a.B = B;
+            a.K = int(p->K[ax]);
+            a.N = int(p->N[ax]);
+            a.rows = 1;
+            for (int b = 0; b < d - 1; ++b) a.rows *= p->N[b];
+            a.d = d;
+            for (int b = 0; b < d; ++b) {
+                a.Nax[b] = int(p->N[b]);
+                a.scale[b] = p->scale[b];
+            }
+            HIP_TRY(launch_last_pass(a, s), "adjoint last FFT pass");
+        } else {
+            float2 *dst = (ax % 2 == 0) ? p->tmp : p->grid;
+            StridedPassArgs a{};
+            a.in = cur;
+            a.out = dst;
+            a.tw = p->tw[ax];
+            a.rp = p->rp[ax];
+            a.K = int(p->K[ax]);
+            a.Lin = int(p->K[ax]);
+            a.Lout = int(p->N[ax]);
+            a.outer = 1;
+            for (int b = 0; b < ax; ++b) a.outer *= p->N[b];
+            a.inner = 1;
+            for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
+            a.grids = grids;
+            a.inverse = true;
+            HIP_TRY(launch_strided_pass(a, s), "adjoint strided FFT pass");
+            cur = dst;
+        }
+    }
+    return NUFFT_OK;
+}
+
+int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s) {
+    InterpArgs a{};
+    a.geo = p->geom();
+    a.om_sorted = p->om_sorted;
+    a.perm = p->perm;
+    a.M = p->M;
+    a.G = G;
+    a.grid_elems = p->grid_elems;
+    a.grids = grids;
+    a.y = y;
+    HIP_TRY(launch_interp(a, s), "interpolation");
+    return NUFFT_OK;
+}
+
+int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s) {
+    GridArgs a{};
+    a.geo = p->geom();
+    a.om_sorted = p->om_sorted;
+    a.perm = p->perm;
+    a.bin_start = p->bin_start;
+    a.M = p->M;
+    for (int ax = 0; ax < p->d; ++ax) {
+        a.T[ax] = p->T[ax];
+        a.nt[ax] = p->nt[ax];
+        a.R[ax] = p->R[ax];
+    }
+    a.tile_cells = p->tile_cells;
+    a.chunk = p->chunk;
+    a.items = p->items;
+    a.n_items = p->n_items;
+    a.y = y;
+    a.grids = grids;
+    a.h = h;
+    a.grid_elems = p->grid_elems;
+    a.partials = p->partials;
+    a.n_slots = p->n_slots;
+    HIP_TRY(launch_grid(a, s), "gridding");
+    ReduceArgs r{};
+    r.hot = p->hot;
+    r.n_hot = p->n_hot;
+    r.d = p->d;
+    for (int ax = 0; ax < p->d; ++ax) {
+        r.K[ax] = int(p->K[ax]);
+        r.T[ax] = p->T[ax];
+        r.nt[ax] = p->nt[ax];
+    }
+    r.tile_cells = p->tile_cells;
+    r.partials = p->partials;
+    r.n_slots = p->n_slots;
+    r.h = h;
+    r.grid_elems = p->grid_elems;
+    r.grids = grids;
+    HIP_TRY(launch_reduce_partials(r, s), "gridding partial sums");
+    return NUFFT_OK;
+}
+
+int begin_call(nufft_plan_t plan, void *stream) {
+    int st = check_plan(plan);
+    if (st) return st;
+    HIP_TRY(hipSetDevice(plan->device), "select device");
+    plan->last_stream = static_cast<hipStream_t>(stream);
+    return NUFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nufft_status_string(int status) {
+    switch (status) {
+        case NUFFT_OK: return "success";
+        case NUFFT_ERR_INVALID_ARG: return "invalid argument";
+        case NUFFT_ERR_NO_DEVICE: return "no HIP device";
+        case NUFFT_ERR_OOM: return "device out of memory";
+        case NUFFT_ERR_HIP: return "HIP runtime error";
+        case NUFFT_ERR_BAD_PLAN: return "bad plan handle";
+        case NUFFT_ERR_NONFINITE: return "non-finite trajectory coordinate";
+        case NUFFT_ERR_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char *nufft_last_error(void) { return g_last_error.c_str(); }
+
+int nufft_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+int nufft_kernel_weights_host(int J, double sigma, int64_t n, const double *f, double *w, double *dw) {
+    if (J < 2 || J > kMaxJ) return fail(NUFFT_ERR_INVALID_ARG, "J=%d outside [2, %d]", J, kMaxJ);
+    if (!(sigma >= 1.0) || !(sigma < 1e6)) return fail(NUFFT_ERR_INVALID_ARG, "sigma must be >= 1");
+    if (n < 0 || (n > 0 && (!f || !w))) return fail(NUFFT_ERR_INVALID_ARG, "bad arrays");
+    AxisKernel k;
+    if (!kb_fit(J, kb_beta(J, sigma), &k)) return fail(NUFFT_ERR_UNSUPPORTED, "kernel fit did not converge");
+    float wf[kMaxJ], dwf[kMaxJ];
+    for (int64_t i = 0; i < n; ++i) {
+        kb_eval_fit(k, J, float(f[i]), wf, dwf);
+        for (int j = 0; j < J; ++j) {
+            w[i * J + j] = wf[j];
+            if (dw) dw[i * J + j] = dwf[j];
+        }
+    }
+    return NUFFT_OK;
+}
+
+int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, const float *om_dev, void *stream,
+               nufft_plan_t *out) {
+    if (!out) return fail(NUFFT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (d < 1 || d > kMaxDim) return fail(NUFFT_ERR_INVALID_ARG, "d=%d must be 1, 2 or 3", d);
+    if (!N || !K) return fail(NUFFT_ERR_INVALID_ARG, "N or K is NULL");
+    if (J < 2 || J > kMaxJ) return fail(NUFFT_ERR_INVALID_ARG, "J=%d outside [2, %d]", J, kMaxJ);
+    if (M < 0 || M >= (int64_t(1) << 31)) return fail(NUFFT_ERR_INVALID_ARG, "M=%lld out of range", (long long)M);
+    if (M > 0 && !om_dev) return fail(NUFFT_ERR_INVALID_ARG, "om is NULL with M > 0");
+    int64_t img = 1, grd = 1;
+    for (int a = 0; a < d; ++a) {
+        if (N[a] < 2 || N[a] % 2) return fail(NUFFT_ERR_INVALID_ARG, "N[%d]=%lld must be even and >= 2", a, (long long)N[a]);
+        if (K[a] < N[a] || K[a] % 2) return fail(NUFFT_ERR_INVALID_ARG, "K[%d]=%lld must be even and >= N", a, (long long)K[a]);
+        if (K[a] > 8192) return fail(NUFFT_ERR_UNSUPPORTED, "K[%d]=%lld above 8192", a, (long long)K[a]);
+        if (!smooth235(K[a])) return fail(NUFFT_ERR_UNSUPPORTED, "K[%d]=%lld has a prime factor above 5", a, (long long)K[a]);
+        if (J > K[a]) return fail(NUFFT_ERR_INVALID_ARG, "J=%d exceeds K[%d]", J, a);
+        img *= N[a];
+        grd *= K[a];
+    }
+    if (grd >= (int64_t(1) << 31)) return fail(NUFFT_ERR_UNSUPPORTED, "grid of %lld cells too large", (long long)grd);
+    int ndev = 0;
+    hipError_t de = hipGetDeviceCount(&ndev);
+    if (de != hipSuccess || ndev <= 0)
+        return fail(NUFFT_ERR_NO_DEVICE, "no HIP device visible (hipGetDeviceCount: %s, count %d)", hipGetErrorString(de),
+                    ndev);
+
+    nufft_plan_s *p = new (std::nothrow) nufft_plan_s();
+    if (!p) return fail(NUFFT_ERR_OOM, "host allocation failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto bail = [&](int st) {
+        std::string msg = g_last_error;
+        free_plan(p);
+        delete p;
+        g_last_error = msg;
+        return st;
+    };
+    if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(NUFFT_ERR_HIP, "hipGetDevice failed"));
+    p->d = d;
+    p->J = J;
+    p->M = M;
+    p->img_elems = img;
+    p->grid_elems = grd;
+    for (int a = 0; a < d; ++a) {
+        p->N[a] = N[a];
+        p->K[a] = K[a];
+    }
+    // kernel, scaling and FFT constants per axis
+    const int targets[3][3] = {{256, 1, 1}, {32, 32, 1}, {8, 8, 16}};
+    const int need = (J - 1 + 1) / 2;
+    p->tile_cells = 1;
+    p->nbins = 1;
+    for (int a = 0; a < d; ++a) {
+        if (!kb_fit(J, kb_beta(J, double(K[a]) / double(N[a])), &p->ker[a]))
+            return bail(fail(NUFFT_ERR_UNSUPPORTED, "kernel polynomial fit did not converge"));
+        if (!radix_plan(int(K[a]), &p->rp[a])) return bail(fail(NUFFT_ERR_UNSUPPORTED, "no radix plan for K"));
+        p->T[a] = choose_tile(K[a], targets[d - 1][a], std::max(1, need));
+        p->nt[a] = int(K[a] / p->T[a]);
+        p->R[a] = std::min(p->nt[a], 1 + (J - 1 + p->T[a] - 1) / p->T[a]);
+        p->tile_cells *= p->T[a];
+        p->nbins *= p->nt[a];
+        int st;
+        hipError_t e;
+        if ((e = upload(&p->scale[a], kb_scaling(int(N[a]), int(K[a]), J, p->ker[a].beta))) != hipSuccess ||
+            (e = upload(&p->tw[a], twiddles(int(K[a])))) != hipSuccess ||
+            (e = upload(&p->coef[a], p->ker[a].coef)) != hipSuccess ||
+            (e = upload(&p->dcoef[a], p->ker[a].dcoef)) != hipSuccess) {
+            st = hip_fail(e, "upload plan constants");
+            return bail(st);
+        }
+    }
+    if (p->tile_cells > 8192) return bail(fail(NUFFT_ERR_UNSUPPORTED, "gridding tile too large"));
+    if (p->nbins >= (int64_t(1) << 30)) return bail(fail(NUFFT_ERR_UNSUPPORTED, "too many bins"));
+    p->chunk = d == 3 ? 512 : 2048;
+    // intermediate sizes of the FFT passes that land in the tmp buffer
+    p->tmp_elems = 1;
+    for (int pass = 0; pass < d - 1; ++pass) {
+        const int ax = d - 1 - pass;
+        if ((d - 1 - pass) % 2 != 0) {
+            int64_t e = 1;
+            for (int b = 0; b < d; ++b) e *= (b < ax) ? N[b] : K[b];
+            p->tmp_elems = std::max(p->tmp_elems, e);
+        }
+    }
+    for (int ax = 0; ax < d - 1; ++ax) {
+        if (ax % 2 == 0) {
+            int64_t e = 1;
+            for (int b = 0; b < d; ++b) e *= (b <= ax) ? N[b] : K[b];
+            p->tmp_elems = std::max(p->tmp_elems, e);
+        }
+    }
+    {
+        hipError_t e;
+        if ((e = dmalloc(&p->om, size_t(std::max<int64_t>(M, 1)) * d)) != hipSuccess ||
+            (e = dmalloc(&p->om_sorted, size_t(std::max<int64_t>(M, 1)) * d)) != hipSuccess ||
+            (e = dmalloc(&p->perm, size_t(std::max<int64_t>(M, 1)))) != hipSuccess)
+            return bail(hip_fail(e, "allocate trajectory"));
+    }
+    int st = bin_points(p, om_dev, s);
+    if (st) return bail(st);
+    st = ensure_workspace(p, 1);
+    if (st) return bail(st);
+    {
+        std::lock_guard<std::mutex> lk(g_registry_mu);
+        g_registry.insert(p);
+    }
+    *out = p;
+    return NUFFT_OK;
+}
+
+int nufft_set_points(nufft_plan_t plan, const float *om_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (plan->M > 0 && !om_dev) return fail(NUFFT_ERR_INVALID_ARG, "om is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // keep the previous trajectory if the new one is rejected
+    float *old_om = nullptr;
+    const size_t bytes = size_t(plan->M) * plan->d * sizeof(float);
+    if (plan->M > 0) {
+        HIP_TRY(dmalloc(&old_om, size_t(plan->M) * plan->d), "allocate trajectory backup");
+        HIP_TRY(hipMemcpyAsync(old_om, plan->om, bytes, hipMemcpyDeviceToDevice, s), "backup trajectory");
+    }
+    st = bin_points(plan, om_dev, s);
+    if (st) {
+        std::string msg = g_last_error;
+        if (old_om) (void)bin_points(plan, old_om, s);
+        dfree(old_om);
+        g_last_error = msg;
+        return st;
+    }
+    dfree(old_om);
+    return ensure_workspace(plan, std::max(plan->cap_grids, 1));
+}
+
+int nufft_set_coils(nufft_plan_t plan, int C, const void *c_dev) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (C < 0 || (C > 0 && !c_dev)) return fail(NUFFT_ERR_INVALID_ARG, "bad coil arguments");
+    HIP_TRY(hipSetDevice(plan->device), "select device");
+    HIP_TRY(hipDeviceSynchronize(), "synchronise before changing coils");
+    dfree(plan->coils);
+    if (C == 0) {
+        plan->coil_mode = false;
+        plan->C = 1;
+        return NUFFT_OK;
+    }
+    HIP_TRY(dmalloc(&plan->coils, size_t(C) * plan->img_elems), "allocate coil maps");
+    HIP_TRY(hipMemcpy(plan->coils, c_dev, size_t(C) * plan->img_elems * sizeof(float2), hipMemcpyDeviceToDevice),
+            "copy coil maps");
+    plan->coil_mode = true;
+    plan->C = C;
+    return ensure_workspace(plan, C);
+}
+
+int nufft_reserve(nufft_plan_t plan, int B) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (B < 1) return fail(NUFFT_ERR_INVALID_ARG, "B must be >= 1");
+    HIP_TRY(hipSetDevice(plan->device), "select device");
+    const int C = plan->coil_mode ? plan->C : 1;
+    return ensure_workspace(plan, B * C);
+}
+
+int nufft_forward_batched(nufft_plan_t plan, int B, const void *x_dev, void *y_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (B < 1) return fail(NUFFT_ERR_INVALID_ARG, "B must be >= 1");
+    if (!x_dev || (!y_dev && plan->M > 0)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    const int C = plan->coil_mode ? plan->C : 1;
+    if ((st = ensure_workspace(plan, B * C))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = run_fs(plan, static_cast<const float2 *>(x_dev), B, plan->grid, s))) return st;
+    return run_v(plan, plan->grid, B * C, static_cast<float2 *>(y_dev), s);
+}
+
+int nufft_adjoint_batched(nufft_plan_t plan, int B, const void *y_dev, void *x_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (B < 1) return fail(NUFFT_ERR_INVALID_ARG, "B must be >= 1");
+    if (!x_dev || (!y_dev && plan->M > 0)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    const int C = plan->coil_mode ? plan->C : 1;
+    if ((st = ensure_workspace(plan, B * C))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = run_vh(plan, static_cast<const float2 *>(y_dev), B * C, plan->grid, s))) return st;
+    return run_shfh(plan, plan->grid, B, static_cast<float2 *>(x_dev), s);
+}
+
+int nufft_forward(nufft_plan_t plan, const void *x_dev, void *y_dev, void *stream) {
+    return nufft_forward_batched(plan, 1, x_dev, y_dev, stream);
+}
+
+int nufft_adjoint(nufft_plan_t plan, const void *y_dev, void *x_dev, void *stream) {
+    return nufft_adjoint_batched(plan, 1, y_dev, x_dev, stream);
+}
+
+int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev, float *gom_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (!x_dev || ((!gy_dev || !gom_dev) && plan->M > 0)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    const int C = plan->coil_mode ? plan->C : 1;
+    if ((st = ensure_workspace(plan, C))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = run_fs(plan, static_cast<const float2 *>(x_dev), 1, plan->grid, s))) return st;
+    GradArgs a{};
+    a.geo = plan->geom();
+    a.om_sorted = plan->om_sorted;
+    a.perm = plan->perm;
+    a.M = plan->M;
+    a.G = plan->grid;
+    a.grid_elems = plan->grid_elems;
+    a.grids = C;
+    a.gy = static_cast<const float2 *>(gy_dev);
+    a.gom = gom_dev;
+    HIP_TRY(launch_grad(a, s), "trajectory gradient");
+    return NUFFT_OK;
+}
+
+int nufft_stage_fs(nufft_plan_t plan, const void *x_dev, void *G_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (!x_dev || !G_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    if (plan->coil_mode) return fail(NUFFT_ERR_UNSUPPORTED, "stage calls take no coils");
+    return run_fs(plan, static_cast<const float2 *>(x_dev), 1, static_cast<float2 *>(G_dev),
+                  static_cast<hipStream_t>(stream));
+}
+
+int nufft_stage_v(nufft_plan_t plan, const void *G_dev, void *y_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (!G_dev || (!y_dev && plan->M > 0)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    return run_v(plan, static_cast<const float2 *>(G_dev), 1, static_cast<float2 *>(y_dev),
+                 static_cast<hipStream_t>(stream));
+}
+
+int nufft_stage_vh(nufft_plan_t plan, const void *y_dev, void *h_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (!h_dev || (!y_dev && plan->M > 0)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    return run_vh(plan, static_cast<const float2 *>(y_dev), 1, static_cast<float2 *>(h_dev),
+                  static_cast<hipStream_t>(stream));
+}
+
+int nufft_stage_shfh(nufft_plan_t plan, const void *h_dev, void *x_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (!h_dev || !x_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    if (plan->coil_mode) return fail(NUFFT_ERR_UNSUPPORTED, "stage calls take no coils");
+    return run_shfh(plan, static_cast<const float2 *>(h_dev), 1, static_cast<float2 *>(x_dev),
+                    static_cast<hipStream_t>(stream));
+}
+
+int nufft_plan_info(nufft_plan_t plan, double *beta3, int *poly_degree, int *tile3, int64_t *n_bins,
+                    int64_t *n_items, int64_t *workspace_bytes) {
+    int st = check_plan(plan);
+    if (st) return st;
+    for (int a = 0; a < 3; ++a) {
+        if (beta3) beta3[a] = a < plan->d ? plan->ker[a].beta : 0.0;
+        if (tile3) tile3[a] = a < plan->d ? plan->T[a] : 1;
+    }
+    if (poly_degree) *poly_degree = plan->ker[0].deg;
+    if (n_bins) *n_bins = plan->nbins;
+    if (n_items) *n_items = plan->n_items;
+    if (workspace_bytes)
+        *workspace_bytes = int64_t(plan->cap_grids) *
+                           (plan->grid_elems + plan->tmp_elems + std::max<int64_t>(plan->n_slots, 1) * plan->tile_cells) *
+                           int64_t(sizeof(float2));
+    return NUFFT_OK;
+}
+
+int nufft_destroy(nufft_plan_t plan) {
+    int st = check_plan(plan);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_registry_mu);
+        g_registry.erase(plan);
+    }
+    (void)hipSetDevice(plan->device);
+    if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    plan->magic = 0;
+    delete plan;
+    return NUFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Internal declarations shared by the runtime (plan, C ABI) and the HIP
+// kernels of libnufft_mi355x.  Not installed; the public interface is
+// include/nufft_mi355x.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace nufft {
+
+constexpr int kMaxDim = 3;
+constexpr int kMaxJ = 16;
+constexpr int kMaxPasses = 16;     // radix passes per axis (K <= 8192)
+constexpr int kMaxNeighbors = 27;  // bins whose windows can reach one tile
+constexpr int kFftTileElems = 8192;  // complex elements of one FFT workgroup tile (64 KiB LDS)
+constexpr int kFftThreads = 512;
+constexpr int kMaxPolyDeg = 23;
+
+// Radix schedule of one FFT axis (Stockham, product of r[] == K).
+struct RadixPlan {
+    int n;
+    int r[kMaxPasses];
+};
+
+// Kaiser-Bessel kernel of one axis (unnormalised, phi(0) = I0(beta)) as per-tap
+// polynomials in z = 2f - 1, f in [0, 1) the offset of the first tap:
+// w_j(z) = sum_k c[j][k] z^k (k <= deg), and the same for d phi / d t.
+struct AxisKernel {
+    double beta;
+    int deg;       // polynomial degree of w_j
+    int deg_d;     // polynomial degree of the derivative fit
+    std::vector<float> coef;   // [J][deg+1]
+    std::vector<float> dcoef;  // [J][deg_d+1]
+};
+
+// ---- host-side mathematics (kb_host.cpp)
+double kb_beta(int J, double sigma);
+double kb_i0(double z);
+double kb_phi(double t, int J, double beta);
+double kb_dphi(double t, int J, double beta);
+double kb_ft(double xi, int J, double beta);       // continuous Fourier transform
+// Fit the kernel and its derivative per tap; returns false if no degree
+// up to kMaxPolyDeg reaches the target accuracy.
+bool kb_fit(int J, double beta, AxisKernel *out);
+// Evaluate the fitted polynomials exactly as the GPU does (float32 Horner).
+void kb_eval_fit(const AxisKernel &k, int J, float f, float *w, float *dw);
+// Scaling table s(i) = 1 / Phi((i - N/2)/K), i in [0, N) (float32).
+std::vector<float> kb_scaling(int N, int K, int J, double beta);
+// Twiddles e^{-2 pi i e / K}, e in [0, K), computed in float64.
+std::vector<float2> twiddles(int K);
+// Stockham radix schedule; false if K has a prime factor above 5.
+bool radix_plan(int K, RadixPlan *rp);
+
+// ---- device kernel launchers (kernels.hip).  All asynchronous on `s`.
+
+// Forward pass along the contiguous last axis: pad N -> K, scaling, coil
+// multiply; x [B][rows][N] -> out [B*C][rows][K].
+struct FirstPassArgs {
+    const float2 *x;
+    float2 *out;
+    const float2 *tw;
+    RadixPlan rp;
+    const float2 *coils;  // [C][rows*N] or nullptr
+    int C;                // grids per image (1 without coils)
+    int B;                // images
+    int K, N;             // last axis
+    int64_t rows;         // prod_{a<d-1} N_a
+    int d;
+    int Nax[kMaxDim];
+    const float *scale[kMaxDim];
+};
+hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s);
+
+// Pass along a strided axis: [G][outer][Lin][inner] -> [G][outer][Lout][inner],
+// Lin < K means zero padded input rows, Lout < K a cropped output.
+struct StridedPassArgs {
+    const float2 *in;
+    float2 *out;
+    const float2 *tw;
+    RadixPlan rp;
+    int K, Lin, Lout;
+    int64_t outer, inner;
+    int64_t grids;
+    bool inverse;
+};
+hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s);
+
+// Inverse pass along the contiguous last axis with crop K -> N, scaling and
+// coil combination: in [B*C][rows][K] -> x [B][rows][N].
+struct LastPassArgs {
+    const float2 *in;
+    float2 *x;
+    const float2 *tw;
+    RadixPlan rp;
+    const float2 *coils;
+    int C, B;
+    int K, N;
+    int64_t rows;
+    int d;
+    int Nax[kMaxDim];
+    const float *scale[kMaxDim];
+};
+hipError_t launch_last_pass(const LastPassArgs &a, hipStream_t s);
+
+// Geometry shared by the sample kernels.
+struct SampleGeom {
+    int d;
+    int J;
+    int K[kMaxDim];
+    double C[kMaxDim];   // K_a / (2 pi)
+    int deg[kMaxDim];
+    int deg_d[kMaxDim];
+    const float *coef[kMaxDim];   // [J][deg+1]
+    const float *dcoef[kMaxDim];  // [J][deg_d+1]
+};
+
+// Interpolation V: y[g][perm[i]] = sum_taps w * G[g][..] for sorted sample i.
+struct InterpArgs {
+    SampleGeom geo;
+    const float *om_sorted;  // [M][d]
+    const int *perm;         // sorted -> caller order
+    int64_t M;
+    const float2 *G;
+    int64_t grid_elems;
+    int grids;
+    float2 *y;               // [grids][M]
+};
+hipError_t launch_interp(const InterpArgs &a, hipStream_t s);
+
+// Gridding V^H, output driven: one work item per (tile, chunk); tiles that
+// need more than one chunk write partial tiles that reduce_partials sums.
+struct GridItem {
+    int tile;
+    int chunk;
+    int nchunks;
+    int slot;  // first partial slot of the tile (nchunks > 1)
+};
+struct HotTile {
+    int tile;
+    int slot;
+    int nchunks;
+    int pad;
+};
+struct GridArgs {
+    SampleGeom geo;
+    const float *om_sorted;
+    const int *perm;
+    const int *bin_start;  // [nbins + 1]
+    int64_t M;
+    int T[kMaxDim];
+    int nt[kMaxDim];
+    int R[kMaxDim];
+    int tile_cells;
+    int chunk;  // samples per work item
+    const GridItem *items;
+    int64_t n_items;
+    const float2 *y;      // [grids][M] caller order
+    int grids;
+    float2 *h;            // [grids][K^d]
+    int64_t grid_elems;
+    float2 *partials;     // [grids][n_slots][tile_cells]
+    int64_t n_slots;
+};
+hipError_t launch_grid(const GridArgs &a, hipStream_t s);
+
+struct ReduceArgs {
+    const HotTile *hot;
+    int64_t n_hot;
+    int d;
+    int K[kMaxDim];
+    int T[kMaxDim];
+    int nt[kMaxDim];
+    int tile_cells;
+    const float2 *partials;
+    int64_t n_slots;
+    float2 *h;
+    int64_t grid_elems;
+    int grids;
+};
+hipError_t launch_reduce_partials(const ReduceArgs &a, hipStream_t s);
+
+// Trajectory gradient: gom[perm[i]][a] = sum_g Re(conj(gy[g][perm[i]]) * dy/domega_a).
+struct GradArgs {
+    SampleGeom geo;
+    const float *om_sorted;
+    const int *perm;
+    int64_t M;
+    const float2 *G;
+    int64_t grid_elems;
+    int grids;
+    const float2 *gy;  // [grids][M]
+    float *gom;        // [M][d]
+};
+hipError_t launch_grad(const GradArgs &a, hipStream_t s);
+
+// Plan-time binning.
+struct BinArgs {
+    const float *om;
+    int64_t M;
+    int d;
+    int K[kMaxDim];
+    double C[kMaxDim];
+    int J;
+    int T[kMaxDim];
+    int nt[kMaxDim];
+    int *keys;
+    int *counts;
+    int *flag;  // set to 1 on a non-finite coordinate
+};
+hipError_t launch_bin_keys(const BinArgs &a, hipStream_t s);
+hipError_t launch_iota(int *v, int64_t n, hipStream_t s);
+hipError_t launch_permute_points(const float *om, const int *perm, int64_t M, int d, float *om_sorted,
+                                 hipStream_t s);
+// Stable sort of (key, value) pairs with hipCUB; temp storage is allocated
+// and freed inside (plan time only).
+hipError_t sort_pairs(const int *keys_in, int *keys_out, const int *vals_in, int *vals_out, int64_t n,
+                      int key_bits, hipStream_t s);
+
+}  // namespace nufft

@@ -1,0 +1,223 @@
+"""Python face of the C ABI: a NUFFT plan over torch device tensors.
+
+Every method marshals tensor pointers and the current HIP stream into the
+library; all arithmetic runs in the library's HIP kernels.  Images are
+complex64 [*N] (C order), samples complex64 [M], trajectories float32 [M, d]
+in radians (paper Section 2.1: A = V F S and A^H = S^H F^H V^H).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, shape, name: str, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """NUFFT plan for image size N, oversampled grid K, J taps per axis and the
+    trajectory `om` (float32 [M, d] on a HIP device).  Optional `coils`
+    (complex64 [C, *N]) switch on coil mode (paper Section 2.2)."""
+
+    def __init__(self, om: torch.Tensor, N, K=None, J: int = 6, coils: torch.Tensor | None = None):
+        N = tuple(int(n) for n in N)
+        d = len(N)
+        K = tuple(2 * n for n in N) if K is None else tuple(int(k) for k in K)
+        if om.dim() != 2 or om.shape[1] != d:
+            raise ValueError(f"om must be [M, {d}]")
+        self.device = om.device
+        if self.device.type != "cuda":
+            raise ValueError("om must live on a HIP device")
+        om = om.contiguous()
+        self.N, self.K, self.J, self.d = N, K, int(J), d
+        self.M = int(om.shape[0])
+        self.C = 0
+        self._handle = ctypes.c_void_p()
+        n_arr = (ctypes.c_int64 * d)(*N)
+        k_arr = (ctypes.c_int64 * d)(*K)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_plan", d, n_arr, k_arr, self.J, self.M,
+                      _ptr(om) if self.M else ctypes.c_void_p(), _stream(self.device),
+                      ctypes.byref(self._handle))
+        if coils is not None:
+            self.set_coils(coils)
+
+    # ------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            _lib.call("nufft_destroy", self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        if not self._handle.value:
+            raise RuntimeError("plan is closed")
+        return self._handle
+
+    # ------------------------------------------------------------ configuration
+    def set_points(self, om: torch.Tensor):
+        _need(om, torch.float32, (self.M, self.d), "om", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_set_points", self.handle, _ptr(om), _stream(self.device))
+
+    def set_coils(self, coils: torch.Tensor | None):
+        with torch.cuda.device(self.device):
+            torch.cuda.current_stream(self.device).synchronize()
+            if coils is None:
+                _lib.call("nufft_set_coils", self.handle, 0, ctypes.c_void_p())
+                self.C = 0
+                return
+            C = int(coils.shape[0])
+            _need(coils, torch.complex64, (C,) + self.N, "coils", self.device)
+            _lib.call("nufft_set_coils", self.handle, C, _ptr(coils))
+            self.C = C
+
+    def reserve(self, B: int):
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_reserve", self.handle, int(B))
+
+    def info(self) -> dict:
+        beta = (ctypes.c_double * 3)()
+        deg = ctypes.c_int()
+        tile = (ctypes.c_int * 3)()
+        nb, ni, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.call("nufft_plan_info", self.handle, beta, ctypes.byref(deg), tile, ctypes.byref(nb),
+                  ctypes.byref(ni), ctypes.byref(ws))
+        return dict(beta=list(beta)[:self.d], poly_degree=deg.value, tile=list(tile)[:self.d],
+                    n_bins=nb.value, n_items=ni.value, workspace_bytes=ws.value)
+
+    # ------------------------------------------------------------ shapes
+    def _yshape(self, B=None):
+        s = (self.M,)
+        if self.C:
+            s = (self.C,) + s
+        if B is not None:
+            s = (B,) + s
+        return s
+
+    # ------------------------------------------------------------ transforms
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """y = A x (in coil mode y[i] = A (c_i x), shape [C, M])."""
+        _need(x, torch.complex64, self.N, "x", self.device)
+        y = out if out is not None else torch.empty(self._yshape(), dtype=torch.complex64, device=self.device)
+        _need(y, torch.complex64, self._yshape(), "y", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_forward", self.handle, _ptr(x), _ptr(y), _stream(self.device))
+        return y
+
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """x = A^H y (in coil mode sum_i conj(c_i) A^H y[i])."""
+        _need(y, torch.complex64, self._yshape(), "y", self.device)
+        x = out if out is not None else torch.empty(self.N, dtype=torch.complex64, device=self.device)
+        _need(x, torch.complex64, self.N, "x", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_adjoint", self.handle, _ptr(y), _ptr(x), _stream(self.device))
+        return x
+
+    def forward_batched(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        B = int(x.shape[0])
+        _need(x, torch.complex64, (B,) + self.N, "x", self.device)
+        y = out if out is not None else torch.empty(self._yshape(B), dtype=torch.complex64, device=self.device)
+        _need(y, torch.complex64, self._yshape(B), "y", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_forward_batched", self.handle, B, _ptr(x), _ptr(y), _stream(self.device))
+        return y
+
+    def adjoint_batched(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        B = int(y.shape[0])
+        _need(y, torch.complex64, self._yshape(B), "y", self.device)
+        x = out if out is not None else torch.empty((B,) + self.N, dtype=torch.complex64, device=self.device)
+        _need(x, torch.complex64, (B,) + self.N, "x", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_adjoint_batched", self.handle, B, _ptr(y), _ptr(x), _stream(self.device))
+        return x
+
+    def grad_points(self, x: torch.Tensor, gy: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Trajectory gradient (float32 [M, d]) of a real loss through y = A(om) x,
+        given gy = dL/dRe y + i dL/dIm y."""
+        _need(x, torch.complex64, self.N, "x", self.device)
+        _need(gy, torch.complex64, self._yshape(), "gy", self.device)
+        g = out if out is not None else torch.empty((self.M, self.d), dtype=torch.float32, device=self.device)
+        _need(g, torch.float32, (self.M, self.d), "gom", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_grad_points", self.handle, _ptr(x), _ptr(gy), _ptr(g), _stream(self.device))
+        return g
+
+    # ------------------------------------------------------------ stages
+    def stage_fs(self, x: torch.Tensor) -> torch.Tensor:
+        _need(x, torch.complex64, self.N, "x", self.device)
+        G = torch.empty(self.K, dtype=torch.complex64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_stage_fs", self.handle, _ptr(x), _ptr(G), _stream(self.device))
+        return G
+
+    def stage_v(self, G: torch.Tensor) -> torch.Tensor:
+        _need(G, torch.complex64, self.K, "G", self.device)
+        y = torch.empty(self.M, dtype=torch.complex64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_stage_v", self.handle, _ptr(G), _ptr(y), _stream(self.device))
+        return y
+
+    def stage_vh(self, y: torch.Tensor) -> torch.Tensor:
+        _need(y, torch.complex64, (self.M,), "y", self.device)
+        h = torch.empty(self.K, dtype=torch.complex64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_stage_vh", self.handle, _ptr(y), _ptr(h), _stream(self.device))
+        return h
+
+    def stage_shfh(self, h: torch.Tensor) -> torch.Tensor:
+        _need(h, torch.complex64, self.K, "h", self.device)
+        x = torch.empty(self.N, dtype=torch.complex64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_stage_shfh", self.handle, _ptr(h), _ptr(x), _stream(self.device))
+        return x
+
+
+def kernel_weights_host(J: int, sigma: float, f) -> tuple:
+    """The per-tap weights (and derivatives) the GPU evaluates, computed on the
+    host from the same polynomial fit: arrays [len(f), J]."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).ravel())
+    w = np.empty((f.size, J), np.float64)
+    dw = np.empty((f.size, J), np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _lib.call("nufft_kernel_weights_host", int(J), float(sigma), f.size, f.ctypes.data_as(dp),
+              w.ctypes.data_as(dp), dw.ctypes.data_as(dp))
+    return w, dw
+
+
+def device_count() -> int:
+    return int(_lib.load().nufft_device_count())

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the header declares, validates arguments before touching a
+device, rejects bad handles, and its kernel fit matches the oracle's kernel."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1710_03197_amd import _lib
+
+lib = _lib.load()
+
+
+def _plan(d, N, K, J, M):
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int64 * max(d, 1))(*N)
+    k = (ctypes.c_int64 * max(d, 1))(*K)
+    st = lib.nufft_plan(d, n, k, J, M, ctypes.c_void_p(), ctypes.c_void_p(), ctypes.byref(h))
+    return st, h
+
+
+def test_exports_every_declared_symbol():
+    names = _lib.declared_symbols()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/nufft_mi355x.h but not exported"
+
+
+def test_status_strings():
+    for code in range(-7, 1):
+        assert lib.nufft_status_string(code)
+    assert lib.nufft_status_string(-1) == b"invalid argument"
+    assert lib.nufft_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("d,N,K,J,M,code", [
+    (0, (8,), (16,), 6, 10, -1),           # d out of range
+    (4, (8,), (16,), 6, 10, -1),
+    (2, (7, 8), (16, 16), 6, 0, -1),       # odd N
+    (2, (8, 8), (6, 16), 6, 0, -1),        # K < N
+    (2, (8, 8), (17, 16), 6, 0, -1),       # odd K
+    (2, (8, 8), (16, 16), 1, 0, -1),       # J too small
+    (2, (8, 8), (16, 16), 17, 0, -1),      # J too large
+    (1, (8,), (16,), 6, -5, -1),           # negative M
+    (1, (8,), (16,), 6, 10, -1),           # om NULL with M > 0
+    (1, (8,), (14,), 6, 0, -7),            # prime factor 7
+    (1, (8,), (16384,), 6, 0, -7),         # K above 8192
+])
+def test_plan_argument_validation(d, N, K, J, M, code):
+    st, h = _plan(d, N, K, J, M)
+    assert st == code
+    assert h.value is None
+    assert lib.nufft_last_error()
+
+
+def test_plan_without_device_reports_no_device():
+    if lib.nufft_device_count() > 0:
+        pytest.skip("a device is visible")
+    st, h = _plan(2, (8, 8), (16, 16), 6, 0)
+    assert st == -2
+    assert b"device" in lib.nufft_last_error()
+
+
+def test_bad_handles():
+    assert lib.nufft_destroy(ctypes.c_void_p()) == -5
+    junk = ctypes.create_string_buffer(256)
+    assert lib.nufft_destroy(ctypes.cast(junk, ctypes.c_void_p)) == -5
+    assert lib.nufft_forward(ctypes.cast(junk, ctypes.c_void_p), None, None, None) == -5
+    assert lib.nufft_adjoint(None, None, None, None) == -5
+    assert lib.nufft_plan_info(None, None, None, None, None, None, None) == -5
+
+
+@pytest.mark.parametrize("J,sigma", [(6, 2.0), (4, 2.0), (7, 2.0), (8, 1.5), (16, 2.0), (2, 2.0)])
+def test_kernel_fit_matches_oracle_kernel(orc, J, sigma):
+    """The float32 per-tap polynomials the GPU evaluates agree with the oracle's
+    float64 Kaiser-Bessel kernel to ~1e-7 of its peak."""
+    from paper_1710_03197_amd.plan import kernel_weights_host
+    f = np.linspace(0.0, 1.0, 257, endpoint=False)
+    w, dw = kernel_weights_host(J, sigma, f)
+    beta = orc.kb_beta(J, sigma)
+    p0 = orc.kb_phi(0.0, J, beta)
+    ref = np.array([[orc.kb_phi(fi + J / 2 - 1 - j, J, beta) for j in range(J)] for fi in f])
+    dref = np.array([[orc.kb_dphi(fi + J / 2 - 1 - j, J, beta) for j in range(J)] for fi in f])
+    assert np.abs(w - ref).max() < 4e-7 * p0
+    assert np.abs(dw - dref).max() < 4e-7 * np.abs(dref).max()
+
+
+def test_kernel_fit_rejects_bad_arguments():
+    f = np.zeros(3)
+    w = np.zeros(3 * 6)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.nufft_kernel_weights_host(1, 2.0, 3, f.ctypes.data_as(dp), w.ctypes.data_as(dp), None) == -1
+    assert lib.nufft_kernel_weights_host(6, 0.5, 3, f.ctypes.data_as(dp), w.ctypes.data_as(dp), None) == -1

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded float32 trajectories and complex64 inputs.
+
+Bar: relative L2 error <= 1e-5 (float32 arithmetic against float64), per
+stage and for the whole pair; batched and coil modes agree with looped single
+calls to 1e-6; the adjoint's run-to-run spread stays at float32 rounding.
+"""
+import numpy as np
+import pytest
+
+from nudft import rel_l2
+from paper_1710_03197_amd import data
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev) if dtype is None else \
+        torch.from_numpy(np.ascontiguousarray(a).astype(dtype)).to(dev)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rand_c(shape, seed):
+    r = np.random.default_rng(seed)
+    return (r.standard_normal(shape) + 1j * r.standard_normal(shape)).astype(np.complex64)
+
+
+def _plan(om, N, K, J, dev, coils=None):
+    from paper_1710_03197_amd import Plan
+    return Plan(_t(om, dev), N, K, J, coils=None if coils is None else _t(coils, dev))
+
+
+CASES = [
+    # name, N, K, J, trajectory
+    ("c1_2d_64", (64, 64), (128, 128), 6, lambda: data.radial_2d(32, 128)),
+    ("1d_256", (256,), (512,), 6, lambda: np.random.default_rng(7).uniform(-np.pi, np.pi, (3000, 1)).astype(np.float32)),
+    ("3d_16", (16, 16, 16), (32, 32, 32), 6, lambda: data.koosh_ball_3d(64, 32)),
+    ("2d_ragged_sigma", (20, 30), (40, 48), 6, lambda: np.random.default_rng(8).uniform(-4, 4, (2500, 2)).astype(np.float32)),
+    ("2d_J4_wrap", (32, 48), (64, 96), 4, lambda: np.random.default_rng(9).uniform(-7, 7, (1999, 2)).astype(np.float32)),
+    ("2d_J7_odd", (32, 32), (64, 64), 7, lambda: np.random.default_rng(10).uniform(-np.pi, np.pi, (1500, 2)).astype(np.float32)),
+    ("3d_ragged", (12, 10, 18), (24, 30, 36), 5, lambda: np.random.default_rng(11).uniform(-np.pi, np.pi, (3000, 3)).astype(np.float32)),
+    ("2d_radix35", (192, 160), (384, 320), 6, lambda: data.golden_radial_2d(40, 384)),
+]
+
+
+@pytest.mark.parametrize("name,N,K,J,traj", CASES, ids=[c[0] for c in CASES])
+def test_stagewise_and_pair_parity(orc, dev, name, N, K, J, traj):
+    om = traj()
+    x = _rand_c(N, 1)
+    y_in = _rand_c((om.shape[0],), 2)
+    print(f"case {name} N={N} K={K} J={J} M={om.shape[0]}", flush=True)
+    p = _plan(om, N, K, J, dev)
+    # F S
+    y_o, g_o, G_o = orc.forward(x, om, N, K, J, stages=True)
+    G = p.stage_fs(_t(x, dev))
+    assert rel_l2(_np(G), G_o) < TOL
+    # V on the oracle's grid (rounded to complex64)
+    y_v = p.stage_v(_t(G_o.astype(np.complex64), dev))
+    assert rel_l2(_np(y_v), orc.interp(G_o.astype(np.complex64), om, N, K, J)) < TOL
+    # V^H alone
+    x_o, h_o, H_o = orc.adjoint(y_in, om, N, K, J, stages=True)
+    h = p.stage_vh(_t(y_in, dev))
+    assert rel_l2(_np(h), h_o) < TOL
+    # S^H F^H on the oracle's gridded data
+    x_sh = p.stage_shfh(_t(h_o.astype(np.complex64), dev))
+    assert rel_l2(_np(x_sh), orc.crop_scale(orc.fftn(h_o.astype(np.complex64), +1), N, K, J)) < TOL
+    # whole pair
+    y = p.forward(_t(x, dev))
+    assert rel_l2(_np(y), y_o) < TOL
+    xa = p.adjoint(_t(y_in, dev))
+    assert rel_l2(_np(xa), x_o) < TOL
+    p.close()
+
+
+def test_config2_full_size(orc, dev):
+    c = data.config2()
+    N, K, J, om = c["N"], c["K"], c["J"], c["om"]
+    p = _plan(om, N, K, J, dev)
+    y = _np(p.forward(_t(c["x"], dev)))
+    y_o = orc.forward(c["x"], om, N, K, J)
+    assert rel_l2(y, y_o) < TOL
+    yn = (y_o + data.complex_noise(y_o.shape, 1e-3, c["noise_rng"])).astype(np.complex64)
+    x = _np(p.adjoint(_t(yn, dev)))
+    assert rel_l2(x, orc.adjoint(yn, om, N, K, J)) < TOL
+    info = p.info()
+    assert info["n_items"] > info["n_bins"]  # the radial centre is split into chunks
+    p.close()
+
+
+def test_config3_full_size(orc, dev):
+    c = data.config3()
+    N, K, J, om = c["N"], c["K"], c["J"], c["om"]
+    p = _plan(om, N, K, J, dev)
+    y = _np(p.forward(_t(c["x"], dev)))
+    y_o = orc.forward(c["x"], om, N, K, J)
+    assert rel_l2(y, y_o) < TOL
+    yin = _rand_c(y.shape, 5)
+    x = _np(p.adjoint(_t(yin, dev)))
+    assert rel_l2(x, orc.adjoint(yin, om, N, K, J)) < TOL
+    p.close()
+
+
+def test_adjoint_run_to_run_spread_and_identity(orc, dev):
+    """LDS float atomics sum a tile's contributions in whatever order the waves
+    arrive, so repeated adjoints may differ in the last bits; the spread stays
+    at float32 rounding level."""
+    c = data.config1()
+    N, K, J, om = c["N"], c["K"], c["J"], c["om"]
+    p = _plan(om, N, K, J, dev)
+    y = _t(_rand_c((om.shape[0],), 3), dev)
+    x1 = _np(p.adjoint(y))
+    spread = max(rel_l2(_np(p.adjoint(y)), x1) for _ in range(5))
+    print(f"adjoint run-to-run spread {spread:.2e}")
+    assert spread < 1e-6
+    xs = _rand_c(N, 4)
+    Ax = _np(p.forward(_t(xs, dev))).astype(np.complex128)
+    lhs = np.vdot(_np(y).astype(np.complex128), Ax)
+    rhs = np.vdot(x1.astype(np.complex128), xs.astype(np.complex128))
+    # float32 operator: the identity holds to float32 rounding
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Ax) * np.linalg.norm(_np(y))
+    p.close()
+
+
+def test_empty_trajectory(dev):
+    p = _plan(np.zeros((0, 2), np.float32), (16, 16), (32, 32), 6, dev)
+    y = p.forward(_t(_rand_c((16, 16), 1), dev))
+    assert y.shape == (0,)
+    x = _np(p.adjoint(torch.zeros(0, dtype=torch.complex64, device=dev)))
+    assert np.all(x == 0)
+    p.close()
+
+
+def test_nonfinite_trajectory_rejected(dev):
+    from paper_1710_03197_amd import NufftError, Plan
+    om = np.zeros((100, 2), np.float32)
+    om[17, 1] = np.nan
+    with pytest.raises(NufftError) as ei:
+        Plan(_t(om, dev), (16, 16), (32, 32), 6)
+    assert ei.value.code == "NUFFT_ERR_NONFINITE"
+    good = np.random.default_rng(1).uniform(-3, 3, (100, 2)).astype(np.float32)
+    p = Plan(_t(good, dev), (16, 16), (32, 32), 6)
+    x = _t(_rand_c((16, 16), 2), dev)
+    y0 = _np(p.forward(x))
+    with pytest.raises(NufftError):
+        p.set_points(_t(om, dev))
+    assert np.array_equal(_np(p.forward(x)), y0)  # previous trajectory kept
+    p.close()
+
+
+def test_batched_equals_looped(dev):
+    c = data.config1()
+    N, K, J, om = c["N"], c["K"], c["J"], c["om"]
+    p = _plan(om, N, K, J, dev)
+    xs = np.stack([_rand_c(N, 10 + b) for b in range(3)])
+    yb = _np(p.forward_batched(_t(xs, dev)))
+    for b in range(3):
+        assert rel_l2(yb[b], _np(p.forward(_t(xs[b], dev)))) < 1e-6
+    ys = np.stack([_rand_c((om.shape[0],), 20 + b) for b in range(3)])
+    xb = _np(p.adjoint_batched(_t(ys, dev)))
+    for b in range(3):
+        assert rel_l2(xb[b], _np(p.adjoint(_t(ys[b], dev)))) < 1e-6
+    p.close()
+
+
+def test_coil_mode_matches_oracle(orc, dev):
+    N, K, J = (48, 40), (96, 80), 6
+    om = data.golden_radial_2d(24, 96)
+    coils = data.coil_maps(N, 5, np.random.default_rng(3))
+    x = _rand_c(N, 4)
+    p = _plan(om, N, K, J, dev, coils=coils)
+    y = _np(p.forward(_t(x, dev)))
+    y_o = orc.forward_coils(x, coils, om, N, K, J)
+    assert y.shape == (5, om.shape[0])
+    assert rel_l2(y, y_o) < TOL
+    ys = np.stack([_rand_c((om.shape[0],), 30 + i) for i in range(5)])
+    xa = _np(p.adjoint(_t(ys, dev)))
+    assert rel_l2(xa, orc.adjoint_coils(ys, coils, om, N, K, J)) < TOL
+    # batched coil mode
+    xs = np.stack([x, _rand_c(N, 5)])
+    yb = _np(p.forward_batched(_t(xs, dev)))
+    assert yb.shape == (2, 5, om.shape[0])
+    assert rel_l2(yb[0], y) < 1e-6
+    p.close()
+
+
+def test_many_coils_multiple_rounds(orc, dev):
+    """More coils than one LDS tile holds: the last pass combines coils over
+    several rounds."""
+    N, K, J = (64, 64), (512, 512), 6
+    om = data.golden_radial_2d(8, 256)
+    coils = data.coil_maps(N, 20, np.random.default_rng(6))
+    p = _plan(om, N, K, J, dev, coils=coils)
+    ys = np.stack([_rand_c((om.shape[0],), 40 + i) for i in range(20)])
+    xa = _np(p.adjoint(_t(ys, dev)))
+    assert rel_l2(xa, orc.adjoint_coils(ys, coils, om, N, K, J)) < TOL
+    p.close()
+
+
+def test_trajectory_gradient_matches_oracle(orc, dev):
+    N, K, J = (32, 24), (64, 48), 6
+    om = data.perturb(data.golden_radial_2d(16, 64), K, np.random.default_rng(2))
+    coils = data.coil_maps(N, 3, np.random.default_rng(4))
+    x = _rand_c(N, 5)
+    gy = np.stack([_rand_c((om.shape[0],), 50 + i) for i in range(3)])
+    p = _plan(om, N, K, J, dev, coils=coils)
+    g = _np(p.grad_points(_t(x, dev), _t(gy, dev)))
+    ref = np.zeros((om.shape[0], 2))
+    for i in range(3):
+        G = orc.forward_grid(coils[i].astype(np.complex128) * x, N, K, J)
+        orc.grad_points(G, gy[i], om, N, K, J, out=ref)
+    assert rel_l2(g, ref) < 1e-4
+    p.close()
+
+
+def test_trajectory_gradient_3d(orc, dev):
+    N, K, J = (12, 16, 10), (24, 32, 20), 6
+    om = np.random.default_rng(12).uniform(-np.pi, np.pi, (800, 3)).astype(np.float32)
+    x = _rand_c(N, 6)
+    gy = _rand_c((800,), 7)
+    p = _plan(om, N, K, J, dev)
+    g = _np(p.grad_points(_t(x, dev), _t(gy, dev)))
+    ref = orc.grad_points(orc.forward_grid(x, N, K, J), gy, om, N, K, J)
+    assert rel_l2(g, ref) < 1e-4
+    p.close()
