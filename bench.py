@@ -1,0 +1,322 @@
+#!/usr/bin/env python3
+"""Throughput of the NUFFT forward+adjoint pair (PyNUFFT, arXiv 1710.03197,
+Section 2.1: A = V F S, A^H = S^H F^H V^H) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one forward + adjoint pair on the 2D 256x256 golden-angle radial
+workload (grid 512x512, J = 6, M = 131072, complex64, synthetic seeded data,
+inputs resident in HBM).  Before timing, the pair is checked against the FP64
+oracle at relative L2 <= 1e-5.  Prints one JSON line with pairs/s, the
+roofline of the dominant kernel (per-kernel HIP events recorded by the
+library on the launch stream, in a second loop identical to the timed one),
+the FP64 oracle timed on the host cores, and extra fields for the 3D 128^3
+koosh-ball pair and for coil-batched versus looped single transforms.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "NUFFT fwd+adj pairs/s, 2D 256² & 3D 128³ at rel err≤1e-5; batched vs looped"
+TOL = 1e-5
+
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
+# this benchmark (KiB per dispatch), with the scale factor measured on a plain
+# copy kernel of known size.  Keyed by the sha256 of kernels.hip when the
+# counters were taken: after any change to the kernels the entry no longer
+# applies and traffic is reported as null.
+MEASURED_TRAFFIC: dict = {}
+
+
+def kernels_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1710_03197_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def prod(v):
+    p = 1
+    for a in v:
+        p *= int(a)
+    return p
+
+
+def algorithmic_bytes(N, K, M, J):
+    """Bytes each kernel must move per forward+adjoint pair if every stage
+    reads and writes its arrays exactly once (complex64 = 8 B, float32 om):
+    the FFT passes read the previous stage's array and write theirs (pruned to
+    the non-zero rows), V reads the grid (at most once), om and writes y, V^H
+    reads y and om and writes the grid.  Returns {kernel: bytes per pair}."""
+    d = len(N)
+    out = {}
+
+    def add(name, b):
+        out[name] = out.get(name, 0) + b
+
+    for p in range(d):  # forward passes, last axis first: N_ax rows in, K_ax rows out
+        ax = d - 1 - p
+        lead, tail = prod(N[:ax]), prod(K[ax + 1:])
+        add("k_first_pass" if p == 0 else "k_strided_pass<fwd>", 8 * lead * tail * (N[ax] + K[ax]))
+    for ax in range(d):  # adjoint passes, first axis first: K_ax rows in, N_ax rows out
+        lead, tail = prod(N[:ax]), prod(K[ax + 1:])
+        add("k_last_pass" if ax == d - 1 else "k_strided_pass<inv>", 8 * lead * tail * (K[ax] + N[ax]))
+    add("k_interp", 8 * min(prod(K), M * J ** d) + 4 * d * M + 8 * M)
+    add("k_grid", 8 * M + 4 * d * M + 8 * prod(K))
+    return out
+
+
+def rel_l2(a, b):
+    import numpy as np
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def time_pairs(plan, x, y, xa, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.forward(x, out=y)
+        plan.adjoint(y, out=xa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(x, out=y)
+        plan.adjoint(y, out=xa)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_times(plan, x, y, xa, steps):
+    """Per-kernel launches and mean duration (ms) over `steps` pairs, from the
+    library's HIP events on the launch stream."""
+    import torch
+    torch.cuda.synchronize()
+    plan.timing(True)
+    for _ in range(steps):
+        plan.forward(x, out=y)
+        plan.adjoint(y, out=xa)
+    torch.cuda.synchronize()
+    rep = plan.timing_report()
+    plan.timing(False)
+    return {k: (n / steps, ms / n) for k, (n, ms) in rep.items()}
+
+
+def roofline_entry(ktimes, alg, steps_hash):
+    """Roofline of the kernel with the largest share of the pair's time."""
+    dom = max(ktimes, key=lambda k: ktimes[k][0] * ktimes[k][1])
+    launches_per_pair, avg_ms = ktimes[dom]
+    bytes_per_launch = alg[dom] / launches_per_pair
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    m = MEASURED_TRAFFIC.get(dom)
+    if m and m.get("kernels_sha") == steps_hash:
+        traffic = m["bytes_per_launch"]
+    return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                 "kernel": dom, "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                 "avg_launch_us": round(avg_ms * 1e3, 2)}
+
+
+def bench_2d(dev, steps, warmup, orc_mod):
+    import numpy as np
+    import torch
+    from paper_1710_03197_amd import Plan, data
+    c = data.config2()
+    N, K, J, om = c["N"], c["K"], c["J"], c["om"]
+    M = om.shape[0]
+    print(f"[bench] 2D workload N={N} K={K} J={J} M={M}", flush=True)
+    plan = Plan(torch.from_numpy(om).to(dev), N, K, J)
+    x = torch.from_numpy(c["x"]).to(dev)
+    y = torch.empty(M, dtype=torch.complex64, device=dev)
+    xa = torch.empty(N, dtype=torch.complex64, device=dev)
+    # parity gate at the benchmarked configuration
+    plan.forward(x, out=y)
+    plan.adjoint(y, out=xa)
+    torch.cuda.synchronize()
+    y_np = y.cpu().numpy()
+    err_f = rel_l2(y_np, orc_mod.forward(c["x"], om, N, K, J))
+    err_a = rel_l2(xa.cpu().numpy(), orc_mod.adjoint(y_np, om, N, K, J))
+    print(f"[bench] 2D parity: forward {err_f:.2e}, adjoint {err_a:.2e}", flush=True)
+    if not (err_f <= TOL and err_a <= TOL):
+        raise SystemExit(f"parity gate failed: forward {err_f:.2e}, adjoint {err_a:.2e}")
+    sec = time_pairs(plan, x, y, xa, steps, warmup)
+    ktimes = kernel_times(plan, x, y, xa, steps)
+    alg = algorithmic_bytes(N, K, M, J)
+    info = plan.info()
+    plan.close()
+    return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f, err_a=err_a, N=N, K=K, M=M, J=J, info=info)
+
+
+def bench_3d(dev, steps, warmup, orc_mod):
+    import torch
+    from paper_1710_03197_amd import Plan, data
+    c = data.config3()
+    N, K, J, om = c["N"], c["K"], c["J"], c["om"]
+    M = om.shape[0]
+    print(f"[bench] 3D workload N={N} K={K} J={J} M={M}", flush=True)
+    plan = Plan(torch.from_numpy(om).to(dev), N, K, J)
+    x = torch.from_numpy(c["x"]).to(dev)
+    y = torch.empty(M, dtype=torch.complex64, device=dev)
+    xa = torch.empty(N, dtype=torch.complex64, device=dev)
+    plan.forward(x, out=y)
+    torch.cuda.synchronize()
+    err_f = rel_l2(y.cpu().numpy(), orc_mod.forward(c["x"], om, N, K, J))
+    print(f"[bench] 3D parity: forward {err_f:.2e}", flush=True)
+    if not err_f <= TOL:
+        raise SystemExit(f"3D parity gate failed: forward {err_f:.2e}")
+    sec = time_pairs(plan, x, y, xa, steps, warmup)
+    ktimes = kernel_times(plan, x, y, xa, max(2, steps // 2))
+    alg = algorithmic_bytes(N, K, M, J)
+    plan.close()
+    return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f)
+
+
+def bench_coils(dev, steps, warmup, n_problems=6):
+    """Coil-batched transforms (one call maps an image to its 8 coil sample
+    sets and back) against looped single-coil calls on the same data."""
+    import torch
+    from paper_1710_03197_amd import Plan, data
+    probs = data.config4(n_problems=n_problems)
+    print(f"[bench] coil batch: {n_problems} spiral problems x 8 coils", flush=True)
+    batched, looped = [], []
+    for pr in probs:
+        om = torch.from_numpy(pr["om"]).to(dev)
+        coils = torch.from_numpy(pr["coils"]).to(dev)
+        x = torch.from_numpy(pr["x"]).to(dev)
+        pb = Plan(om, pr["N"], pr["K"], pr["J"], coils=coils)
+        ps = Plan(om, pr["N"], pr["K"], pr["J"])
+        cx = coils * x[None]
+        yb = torch.empty((8, pr["om"].shape[0]), dtype=torch.complex64, device=dev)
+        xb = torch.empty(pr["N"], dtype=torch.complex64, device=dev)
+        batched.append((pb, x, yb, xb))
+        looped.append((ps, cx, yb, torch.empty_like(cx)))
+
+    def run_batched():
+        for pb, x, yb, xb in batched:
+            pb.forward(x, out=yb)
+            pb.adjoint(yb, out=xb)
+
+    def run_looped():
+        for ps, cx, yb, xl in looped:
+            for i in range(cx.shape[0]):
+                ps.forward(cx[i], out=yb[i])
+                ps.adjoint(yb[i], out=xl[i])
+
+    res = {}
+    for name, fn in (("batched", run_batched), ("looped", run_looped)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / steps
+    n_pairs = 8 * len(probs)
+    for pb, *_ in batched:
+        pb.close()
+    for ps, *_ in looped:
+        ps.close()
+    return dict(pairs_per_s_batched=n_pairs / res["batched"], pairs_per_s_looped=n_pairs / res["looped"],
+                speedup=res["looped"] / res["batched"], problems=len(probs), coils=8)
+
+
+def cpu_baseline(orc_mod, budget_s=12.0):
+    """The FP64 oracle pair on the 2D workload, repeated for about budget_s."""
+    from paper_1710_03197_amd import data
+    c = data.config2()
+    N, K, J, om, x = c["N"], c["K"], c["J"], c["om"], c["x"]
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        y = orc_mod.forward(x, om, N, K, J)
+        orc_mod.adjoint(y, om, N, K, J)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    sec = (time.perf_counter() - t0) / reps
+    return {"value": round(1.0 / sec, 3), "unit": "pairs/s", "cores": orc_mod.num_threads(), "kind": "oracle",
+            "sample": f"{reps} full FP64 forward+adjoint pairs of the 2D 256^2 workload (M=131072), "
+                      f"{sec * 1e3:.1f} ms each"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-coils", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    import oracle as orc_mod
+    dev = torch.device("cuda:0")
+    khash = kernels_hash()
+
+    r2 = bench_2d(dev, args.steps, args.warmup, orc_mod)
+    dom, roof = roofline_entry(r2["ktimes"], r2["alg"], khash)
+    extra = {
+        "rel_err_forward": r2["err_f"], "rel_err_adjoint": r2["err_a"],
+        "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r2["ktimes"].items()},
+        "pair_bytes_model": int(sum(r2["alg"].values())),
+        "pair_model_frac": round(sum(r2["alg"].values()) / r2["sec"] / 1e9 / HBM_PEAK_GBS, 4),
+        "plan": r2["info"], "kernels_sha": khash,
+    }
+    if not args.no_3d:
+        r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod)
+        _, roof3 = roofline_entry(r3["ktimes"], r3["alg"], khash)
+        extra["3d_128"] = {
+            "pairs_per_s": round(1.0 / r3["sec"], 2), "ms_per_pair": round(r3["sec"] * 1e3, 4),
+            "rel_err_forward": r3["err_f"],
+            "pair_bytes_model": int(sum(r3["alg"].values())),
+            "pair_model_frac": round(sum(r3["alg"].values()) / r3["sec"] / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r3["ktimes"].items()},
+            "roofline": roof3,
+        }
+    if not args.no_coils:
+        extra["coil_batched_vs_looped"] = bench_coils(dev, max(3, args.steps // 20), 2)
+    cpu = None if args.no_cpu else cpu_baseline(orc_mod, args.cpu_seconds)
+
+    result = {
+        "metric": METRIC,
+        "value": round(1.0 / r2["sec"], 2),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r2["sec"] * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2d_256_golden_radial: image 256x256 complex64 ellipse phantom, grid 512x512 "
+                               "(sigma=2), Kaiser-Bessel J=6, M=131072 golden-angle radial (256 spokes x 512)",
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,16 @@ int nufft_plan_info(nufft_plan_t plan, double *beta3, int *poly_degree, int *til
  * dw[i*J + j] = phi'(f + J/2 - 1 - j) (dw may be NULL).  Needs no device. */
 int nufft_kernel_weights_host(int J, double sigma, int64_t n, const double *f, double *w, double *dw);
 
+/* Per-kernel timing: with enable = 1 the plan records a pair of HIP events on
+ * the launch stream around every kernel it launches (not for graph capture);
+ * enable = 0 stops.  Either call discards the records collected so far.
+ * nufft_timing_read reports, for kernel index k in [0, nufft_timing_kernels()),
+ * its name (static storage), the number of launches recorded and their summed
+ * duration in milliseconds; it waits for the recorded events. */
+int nufft_timing_enable(nufft_plan_t plan, int enable);
+int nufft_timing_kernels(void);
+int nufft_timing_read(nufft_plan_t plan, int kernel, const char **name, int64_t *launches, double *total_ms);
+
 /* Synchronise the plan's last stream and free everything.  A NULL, destroyed
  * or foreign handle returns BAD_PLAN and is not touched. */
 int nufft_destroy(nufft_plan_t plan);

@@ -58,6 +58,9 @@ _SIGS = {
     "nufft_kernel_weights_host": [ctypes.c_int, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp],
     "nufft_destroy": [_vp],
     "nufft_device_count": [],
+    "nufft_timing_enable": [_vp, ctypes.c_int],
+    "nufft_timing_kernels": [],
+    "nufft_timing_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _i64p, _dp],
 }
 
 

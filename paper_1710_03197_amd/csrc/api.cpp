@@ -124,6 +124,14 @@ struct nufft_plan_s {
     float2 *tmp = nullptr;
     float2 *partials = nullptr;
     hipStream_t last_stream = nullptr;
+    // optional per-kernel event timing
+    bool timing = false;
+    struct TimingRec {
+        int kernel;
+        hipEvent_t start, stop;
+    };
+    std::vector<TimingRec> timing_recs;
+    std::vector<hipEvent_t> event_pool;
 
     SampleGeom geom() const {
         SampleGeom g{};
@@ -151,7 +159,47 @@ int check_plan(nufft_plan_t p) {
     return NUFFT_OK;
 }
 
+enum KernelId { kFirstPass, kStridedFwd, kStridedInv, kLastPass, kInterp, kGrid, kReduce, kGrad, kNumKernels };
+const char *const kKernelNames[kNumKernels] = {"k_first_pass", "k_strided_pass<fwd>", "k_strided_pass<inv>",
+                                               "k_last_pass", "k_interp", "k_grid", "k_reduce_partials",
+                                               "k_grad"};
+
+hipError_t take_event(nufft_plan_s *p, hipEvent_t *ev) {
+    if (!p->event_pool.empty()) {
+        *ev = p->event_pool.back();
+        p->event_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+// Launch through `fn`, bracketed by events on `s` when the plan collects timings.
+template <class F>
+hipError_t timed(nufft_plan_s *p, int kernel, hipStream_t s, F fn) {
+    if (!p->timing) return fn();
+    hipEvent_t a, b;
+    hipError_t e = take_event(p, &a);
+    if (e != hipSuccess) return e;
+    if ((e = take_event(p, &b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
+    if ((e = fn()) != hipSuccess) return e;
+    if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+    p->timing_recs.push_back({kernel, a, b});
+    return hipSuccess;
+}
+
+void recycle_timing(nufft_plan_s *p) {
+    for (auto &r : p->timing_recs) {
+        p->event_pool.push_back(r.start);
+        p->event_pool.push_back(r.stop);
+    }
+    p->timing_recs.clear();
+}
+
 void free_plan(nufft_plan_s *p) {
+    recycle_timing(p);
+    for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+    p->event_pool.clear();
     for (int a = 0; a < kMaxDim; ++a) {
         dfree(p->scale[a]);
         dfree(p->tw[a]);
@@ -350,7 +398,7 @@ int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) 
                 a.Nax[b] = int(p->N[b]);
                 a.scale[b] = p->scale[b];
             }
-            HIP_TRY(launch_first_pass(a, s), "forward first FFT pass");
+            HIP_TRY(timed(p, kFirstPass, s, [&] { return launch_first_pass(a, s); }), "forward first FFT pass");
         } else {
             StridedPassArgs a{};
             a.in = cur;
@@ -366,7 +414,7 @@ int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) 
             for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
             a.grids = grids;
             a.inverse = false;
-            HIP_TRY(launch_strided_pass(a, s), "forward strided FFT pass");
+            HIP_TRY(timed(p, kStridedFwd, s, [&] { return launch_strided_pass(a, s); }), "forward strided FFT pass");
         }
         cur = dst;
     }
@@ -398,7 +446,7 @@ int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s) 
                 a.Nax[b] = int(p->N[b]);
                 a.scale[b] = p->scale[b];
             }
-            HIP_TRY(launch_last_pass(a, s), "adjoint last FFT pass");
+            HIP_TRY(timed(p, kLastPass, s, [&] { return launch_last_pass(a, s); }), "adjoint last FFT pass");
         } else {
             float2 *dst = (ax % 2 == 0) ? p->tmp : p->grid;
             StridedPassArgs a{};
@@ -415,7 +463,7 @@ int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s) 
             for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
             a.grids = grids;
             a.inverse = true;
-            HIP_TRY(launch_strided_pass(a, s), "adjoint strided FFT pass");
+            HIP_TRY(timed(p, kStridedInv, s, [&] { return launch_strided_pass(a, s); }), "adjoint strided FFT pass");
             cur = dst;
         }
     }
@@ -432,7 +480,7 @@ int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s)
     a.grid_elems = p->grid_elems;
     a.grids = grids;
     a.y = y;
-    HIP_TRY(launch_interp(a, s), "interpolation");
+    HIP_TRY(timed(p, kInterp, s, [&] { return launch_interp(a, s); }), "interpolation");
     return NUFFT_OK;
 }
 
@@ -458,7 +506,7 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.grid_elems = p->grid_elems;
     a.partials = p->partials;
     a.n_slots = p->n_slots;
-    HIP_TRY(launch_grid(a, s), "gridding");
+    HIP_TRY(timed(p, kGrid, s, [&] { return launch_grid(a, s); }), "gridding");
     ReduceArgs r{};
     r.hot = p->hot;
     r.n_hot = p->n_hot;
@@ -474,7 +522,8 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     r.h = h;
     r.grid_elems = p->grid_elems;
     r.grids = grids;
-    HIP_TRY(launch_reduce_partials(r, s), "gridding partial sums");
+    if (p->n_hot > 0)
+        HIP_TRY(timed(p, kReduce, s, [&] { return launch_reduce_partials(r, s); }), "gridding partial sums");
     return NUFFT_OK;
 }
 
@@ -741,7 +790,7 @@ int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev, 
     a.grids = C;
     a.gy = static_cast<const float2 *>(gy_dev);
     a.gom = gom_dev;
-    HIP_TRY(launch_grad(a, s), "trajectory gradient");
+    HIP_TRY(timed(plan, kGrad, s, [&] { return launch_grad(a, s); }), "trajectory gradient");
     return NUFFT_OK;
 }
 
@@ -794,6 +843,39 @@ int nufft_plan_info(nufft_plan_t plan, double *beta3, int *poly_degree, int *til
         *workspace_bytes = int64_t(plan->cap_grids) *
                            (plan->grid_elems + plan->tmp_elems + std::max<int64_t>(plan->n_slots, 1) * plan->tile_cells) *
                            int64_t(sizeof(float2));
+    return NUFFT_OK;
+}
+
+int nufft_timing_enable(nufft_plan_t plan, int enable) {
+    int st = check_plan(plan);
+    if (st) return st;
+    HIP_TRY(hipSetDevice(plan->device), "select device");
+    if (!plan->timing_recs.empty()) HIP_TRY(hipEventSynchronize(plan->timing_recs.back().stop), "drain timing events");
+    recycle_timing(plan);
+    plan->timing = enable != 0;
+    return NUFFT_OK;
+}
+
+int nufft_timing_kernels(void) { return kNumKernels; }
+
+int nufft_timing_read(nufft_plan_t plan, int kernel, const char **name, int64_t *launches, double *total_ms) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (kernel < 0 || kernel >= kNumKernels) return fail(NUFFT_ERR_INVALID_ARG, "kernel index %d out of range", kernel);
+    if (name) *name = kKernelNames[kernel];
+    HIP_TRY(hipSetDevice(plan->device), "select device");
+    int64_t n = 0;
+    double ms = 0.0;
+    for (auto &r : plan->timing_recs) {
+        if (r.kernel != kernel) continue;
+        HIP_TRY(hipEventSynchronize(r.stop), "wait for timing event");
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, r.start, r.stop), "read timing event");
+        ms += t;
+        ++n;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
     return NUFFT_OK;
 }
 

@@ -120,6 +120,25 @@ class Plan:
         return dict(beta=list(beta)[:self.d], poly_degree=deg.value, tile=list(tile)[:self.d],
                     n_bins=nb.value, n_items=ni.value, workspace_bytes=ws.value)
 
+    def timing(self, enable: bool):
+        """Start (True) or stop (False) per-kernel event timing; both discard
+        what was collected."""
+        _lib.call("nufft_timing_enable", self.handle, 1 if enable else 0)
+
+    def timing_report(self) -> dict:
+        """{kernel name: (launches, total ms)} for kernels launched since
+        timing(True); waits for the recorded events."""
+        out = {}
+        lib = _lib.load()
+        for k in range(lib.nufft_timing_kernels()):
+            name = ctypes.c_char_p()
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            _lib.call("nufft_timing_read", self.handle, k, ctypes.byref(name), ctypes.byref(n), ctypes.byref(ms))
+            if n.value:
+                out[name.value.decode()] = (n.value, ms.value)
+        return out
+
     # ------------------------------------------------------------ shapes
     def _yshape(self, B=None):
         s = (self.M,)
