@@ -11,7 +11,8 @@ oracle at relative L2 <= 1e-5.  Prints one JSON line with pairs/s, the
 roofline of the dominant kernel (per-kernel HIP events recorded by the
 library on the launch stream, in a second loop identical to the timed one),
 the FP64 oracle timed on the host cores, and extra fields for the 3D 128^3
-koosh-ball pair and for coil-batched versus looped single transforms.
+koosh-ball pair and for the uneven multi-problem batch (24 spiral problems x 8
+coils in one graph launch) versus looped single transforms.
 """
 from __future__ import annotations
 
@@ -180,36 +181,48 @@ def bench_3d(dev, steps, warmup, orc_mod):
     return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f)
 
 
-def bench_coils(dev, steps, warmup, n_problems=6):
-    """Coil-batched transforms (one call maps an image to its 8 coil sample
-    sets and back) against looped single-coil calls on the same data."""
+def bench_batched(dev, steps, warmup, orc_mod, n_problems=24):
+    """Config 4: 24 uneven 2D spiral problems x 8 coils.  Batched: one
+    multi-plan (coil maps fused into each problem's launches, all problems in
+    one captured HIP graph).  Looped: a single-coil plan per problem, called
+    once per (problem, coil) with the pre-multiplied image c_i x."""
+    import numpy as np
     import torch
     from paper_1710_03197_amd import Plan, data
+    from paper_1710_03197_amd.plan import MultiPlan
     probs = data.config4(n_problems=n_problems)
-    print(f"[bench] coil batch: {n_problems} spiral problems x 8 coils", flush=True)
-    batched, looped = [], []
-    for pr in probs:
-        om = torch.from_numpy(pr["om"]).to(dev)
-        coils = torch.from_numpy(pr["coils"]).to(dev)
-        x = torch.from_numpy(pr["x"]).to(dev)
-        pb = Plan(om, pr["N"], pr["K"], pr["J"], coils=coils)
-        ps = Plan(om, pr["N"], pr["K"], pr["J"])
-        cx = coils * x[None]
-        yb = torch.empty((8, pr["om"].shape[0]), dtype=torch.complex64, device=dev)
-        xb = torch.empty(pr["N"], dtype=torch.complex64, device=dev)
-        batched.append((pb, x, yb, xb))
-        looped.append((ps, cx, yb, torch.empty_like(cx)))
+    C = probs[0]["coils"].shape[0]
+    print(f"[bench] batched: {len(probs)} spiral problems x {C} coils, "
+          f"M {min(p['om'].shape[0] for p in probs)}..{max(p['om'].shape[0] for p in probs)}", flush=True)
+    oms = [torch.from_numpy(p["om"]).to(dev) for p in probs]
+    coils = [torch.from_numpy(p["coils"]).to(dev) for p in probs]
+    xs = [torch.from_numpy(p["x"]).to(dev) for p in probs]
+    mp = MultiPlan([dict(om=o, N=p["N"], coils=c) for o, p, c in zip(oms, probs, coils)], J=6)
+    ys = mp.forward(xs)
+    xa = mp.adjoint(ys)
+    torch.cuda.synchronize()
+    errs = []
+    for p in (0, len(probs) - 1):  # parity at the same accuracy before timing
+        pr = probs[p]
+        yo = orc_mod.forward_coils(pr["x"], pr["coils"], pr["om"], pr["N"], pr["K"], 6)
+        errs.append(rel_l2(ys[p].cpu().numpy(), yo))
+    print(f"[bench] batched parity: {[f'{e:.2e}' for e in errs]}", flush=True)
+    if max(errs) > TOL:
+        raise SystemExit("batched parity gate failed")
+    singles = [Plan(o, p["N"], p["K"], 6) for o, p in zip(oms, probs)]
+    cxs = [c * x[None] for c, x in zip(coils, xs)]
+    ybuf = [torch.empty((C, p["om"].shape[0]), dtype=torch.complex64, device=dev) for p in probs]
+    xbuf = [torch.empty_like(cx) for cx in cxs]
 
     def run_batched():
-        for pb, x, yb, xb in batched:
-            pb.forward(x, out=yb)
-            pb.adjoint(yb, out=xb)
+        mp.forward(xs, ys)
+        mp.adjoint(ys, xa)
 
     def run_looped():
-        for ps, cx, yb, xl in looped:
-            for i in range(cx.shape[0]):
-                ps.forward(cx[i], out=yb[i])
-                ps.adjoint(yb[i], out=xl[i])
+        for sp, cx, yb, xb in zip(singles, cxs, ybuf, xbuf):
+            for i in range(C):
+                sp.forward(cx[i], out=yb[i])
+                sp.adjoint(yb[i], out=xb[i])
 
     res = {}
     for name, fn in (("batched", run_batched), ("looped", run_looped)):
@@ -221,13 +234,14 @@ def bench_coils(dev, steps, warmup, n_problems=6):
             fn()
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) / steps
-    n_pairs = 8 * len(probs)
-    for pb, *_ in batched:
-        pb.close()
-    for ps, *_ in looped:
-        ps.close()
-    return dict(pairs_per_s_batched=n_pairs / res["batched"], pairs_per_s_looped=n_pairs / res["looped"],
-                speedup=res["looped"] / res["batched"], problems=len(probs), coils=8)
+    n_pairs = C * len(probs)
+    mp.close()
+    for sp in singles:
+        sp.close()
+    return dict(pairs_per_s_batched=round(n_pairs / res["batched"], 1),
+                pairs_per_s_looped=round(n_pairs / res["looped"], 1),
+                speedup=round(res["looped"] / res["batched"], 3), problems=len(probs), coils=C,
+                ms_per_batch_batched=round(res["batched"] * 1e3, 3), rel_err=max(errs))
 
 
 def cpu_baseline(orc_mod, budget_s=12.0):
@@ -255,7 +269,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-3d", action="store_true")
-    ap.add_argument("--no-coils", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -291,8 +305,8 @@ def main():
             "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r3["ktimes"].items()},
             "roofline": roof3,
         }
-    if not args.no_coils:
-        extra["coil_batched_vs_looped"] = bench_coils(dev, max(3, args.steps // 20), 2)
+    if not args.no_batched:
+        extra["batched_vs_looped"] = bench_batched(dev, max(3, args.steps // 40), 2, orc_mod)
     cpu = None if args.no_cpu else cpu_baseline(orc_mod, args.cpu_seconds)
 
     result = {

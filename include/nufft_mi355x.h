@@ -153,6 +153,39 @@ int nufft_timing_enable(nufft_plan_t plan, int enable);
 int nufft_timing_kernels(void);
 int nufft_timing_read(nufft_plan_t plan, int kernel, const char **name, int64_t *launches, double *total_ms);
 
+/* ---- Many uneven problems in one launch (Section 2.1 batch mode, Section 2.2
+ * coils): P independent transforms with their own sizes, trajectories and
+ * coil maps, all with the same d and J. */
+typedef struct {
+    int d;              /* 1, 2 or 3 (the same for every problem) */
+    int64_t N[3];       /* image size (first d used) */
+    int64_t K[3];       /* grid size (first d used) */
+    int J;              /* taps per axis (the same for every problem) */
+    int64_t M;          /* samples */
+    const float *om;    /* device float32 [M][d], copied */
+    int C;              /* coils, 0 = none */
+    const void *coils;  /* device complex64 [C][N^d] or NULL, copied */
+} nufft_problem_t;
+
+typedef struct nufft_multi_s *nufft_multi_t;
+
+/* Plan P problems (1 <= P <= 256); synchronous.  Errors as nufft_plan, plus
+ * UNSUPPORTED when d or J differ between problems. */
+int nufft_multi_plan(int P, const nufft_problem_t *probs, void *stream, nufft_multi_t *out);
+
+/* x[p] complex64 [N_p^d] -> y[p] complex64 [M_p] ([C_p][M_p] with coils) for
+ * every p, and back.  x and y are host arrays of P device pointers.  The
+ * first call for a given set of pointers captures all P transform sequences
+ * into one HIP graph (forked over several streams so independent problems may
+ * overlap); later calls with the same pointers replay it with one launch.
+ * Asynchronous on `stream`. */
+int nufft_multi_forward(nufft_multi_t m, const void *const *x_dev, void *const *y_dev, void *stream);
+int nufft_multi_adjoint(nufft_multi_t m, const void *const *y_dev, void *const *x_dev, void *stream);
+
+/* Synchronises and frees the sub-plans and cached graphs; a NULL or foreign
+ * handle returns BAD_PLAN. */
+int nufft_multi_destroy(nufft_multi_t m);
+
 /* Synchronise the plan's last stream and free everything.  A NULL, destroyed
  * or foreign handle returns BAD_PLAN and is not touched. */
 int nufft_destroy(nufft_plan_t plan);

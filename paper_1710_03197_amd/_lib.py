@@ -35,6 +35,14 @@ class NufftError(RuntimeError):
 
 _lib = None
 
+
+class ProblemDesc(ctypes.Structure):
+    """nufft_problem_t of include/nufft_mi355x.h."""
+    _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int64 * 3), ("K", ctypes.c_int64 * 3),
+                ("J", ctypes.c_int), ("M", ctypes.c_int64), ("om", ctypes.c_void_p),
+                ("C", ctypes.c_int), ("coils", ctypes.c_void_p)]
+
+
 _vp = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -59,6 +67,10 @@ _SIGS = {
     "nufft_destroy": [_vp],
     "nufft_device_count": [],
     "nufft_timing_enable": [_vp, ctypes.c_int],
+    "nufft_multi_plan": [ctypes.c_int, ctypes.POINTER(ProblemDesc), _vp, ctypes.POINTER(_vp)],
+    "nufft_multi_forward": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
+    "nufft_multi_adjoint": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
+    "nufft_multi_destroy": [_vp],
     "nufft_timing_kernels": [],
     "nufft_timing_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _i64p, _dp],
 }

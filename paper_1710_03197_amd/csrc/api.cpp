@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -107,9 +108,15 @@ struct nufft_plan_s {
     float *om = nullptr;
     float *om_sorted = nullptr;
     int *perm = nullptr;
-    int *bin_start = nullptr;
+    int *sub_start = nullptr;  // [nbins * 2^d + 1]
     GridItem *items = nullptr;
     int64_t n_items = 0;
+    InterpItem *iitems = nullptr;  // nullptr: the gather reads the grid directly
+    int64_t n_iitems = 0;
+    bool staged_interp = true;
+    int seg_len = 16, segs = 1;
+    int group_lanes = 64;
+    int stage_floats = 0;
     HotTile *hot = nullptr;
     int64_t n_hot = 0;
     int64_t n_slots = 0;
@@ -209,8 +216,9 @@ void free_plan(nufft_plan_s *p) {
     dfree(p->om);
     dfree(p->om_sorted);
     dfree(p->perm);
-    dfree(p->bin_start);
+    dfree(p->sub_start);
     dfree(p->items);
+    dfree(p->iitems);
     dfree(p->hot);
     dfree(p->coils);
     dfree(p->grid);
@@ -219,8 +227,8 @@ void free_plan(nufft_plan_s *p) {
 }
 
 // Tile edge on one axis: the largest divisor of K that is <= target, raised
-// to the smallest divisor >= need when it would be smaller (so a window of
-// J taps reaches at most three tiles per axis).
+// to the smallest divisor >= need = J - 1 when it would be smaller, so a
+// window of J taps reaches at most two tiles per axis.
 int choose_tile(int64_t K, int target, int need) {
     int best = 1;
     for (int64_t t = 1; t <= K && t <= target; ++t)
@@ -240,10 +248,11 @@ int bits_for(int64_t n) {
 }
 
 // Bin the trajectory om (device, caller order) into the plan: sorted copy,
-// permutation, bin offsets, scatter work items.  Synchronous.
+// permutation, sub-bin offsets, gather and gridding work items.  Synchronous.
 int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
     const int64_t M = p->M;
     const int d = p->d;
+    const int64_t nkeys = p->nbins << d;
     if (M > 0) HIP_TRY(hipMemcpyAsync(p->om, om_dev, size_t(M) * d * sizeof(float), hipMemcpyDeviceToDevice, s),
                        "copy trajectory");
     int *keys = nullptr, *keys_sorted = nullptr, *iota = nullptr, *counts = nullptr, *flag = nullptr;
@@ -254,16 +263,16 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         dfree(counts);
         dfree(flag);
     };
-    std::vector<int> hcounts(size_t(p->nbins), 0);
+    std::vector<int> hcounts(size_t(nkeys), 0);
     int hflag = 0;
     hipError_t e = hipSuccess;
     do {
         if ((e = dmalloc(&keys, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
         if ((e = dmalloc(&keys_sorted, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
         if ((e = dmalloc(&iota, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
-        if ((e = dmalloc(&counts, size_t(p->nbins))) != hipSuccess) break;
+        if ((e = dmalloc(&counts, size_t(nkeys))) != hipSuccess) break;
         if ((e = dmalloc(&flag, 1)) != hipSuccess) break;
-        if ((e = hipMemsetAsync(counts, 0, size_t(p->nbins) * sizeof(int), s)) != hipSuccess) break;
+        if ((e = hipMemsetAsync(counts, 0, size_t(nkeys) * sizeof(int), s)) != hipSuccess) break;
         if ((e = hipMemsetAsync(flag, 0, sizeof(int), s)) != hipSuccess) break;
         BinArgs ba{};
         ba.om = p->om;
@@ -281,13 +290,13 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         ba.flag = flag;
         if ((e = launch_bin_keys(ba, s)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
-        if ((e = hipMemcpyAsync(hcounts.data(), counts, size_t(p->nbins) * sizeof(int), hipMemcpyDeviceToHost,
-                                s)) != hipSuccess)
+        if ((e = hipMemcpyAsync(hcounts.data(), counts, size_t(nkeys) * sizeof(int), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
             break;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
         if (hflag) break;
         if ((e = launch_iota(iota, M, s)) != hipSuccess) break;
-        if ((e = sort_pairs(keys, keys_sorted, iota, p->perm, M, bits_for(p->nbins), s)) != hipSuccess) break;
+        if ((e = sort_pairs(keys, keys_sorted, iota, p->perm, M, bits_for(nkeys), s)) != hipSuccess) break;
         if ((e = launch_permute_points(p->om, p->perm, M, d, p->om_sorted, s)) != hipSuccess) break;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
     } while (false);
@@ -295,15 +304,16 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "binning the trajectory");
     if (hflag) return fail(NUFFT_ERR_NONFINITE, "trajectory has a NaN, infinite or out-of-range coordinate");
 
-    // bin offsets
-    std::vector<int> start(size_t(p->nbins) + 1, 0);
-    for (int64_t b = 0; b < p->nbins; ++b) start[b + 1] = start[b] + hcounts[b];
-    // scatter work items: per tile, the samples of the distinct bins whose
-    // windows can reach it, split into chunks
+    // sub-bin offsets: sorted order is (tile, crossing code), stable in the caller's order
+    std::vector<int> start(size_t(nkeys) + 1, 0);
+    for (int64_t k = 0; k < nkeys; ++k) start[k + 1] = start[k] + hcounts[k];
+    // gridding work items: per tile, the samples whose windows reach it, in chunks
     std::vector<GridItem> items;
     std::vector<HotTile> hot;
+    std::vector<InterpItem> iitems;
     int64_t slots = 0;
     items.reserve(size_t(p->nbins));
+    const int ichunk = 256 * kInterpSamplesPerThread;
     for (int64_t t = 0; t < p->nbins; ++t) {
         int tc[kMaxDim];
         int64_t rem = t;
@@ -311,24 +321,10 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
             tc[a] = int(rem % p->nt[a]);
             rem /= p->nt[a];
         }
+        int lo[kMaxNeighbors], hi[kMaxNeighbors];
+        const int nseg = tile_segments(d, tc, p->nt, p->R, start.data(), lo, hi);
         int64_t S = 0;
-        int r[kMaxDim] = {0, 0, 0};
-        while (true) {
-            int64_t bin = 0;
-            for (int a = 0; a < d; ++a) {
-                int bt = tc[a] - r[a];
-                if (bt < 0) bt += p->nt[a];
-                bin = bin * p->nt[a] + bt;
-            }
-            S += hcounts[bin];
-            int a = d - 1;
-            while (a >= 0) {
-                if (++r[a] < p->R[a]) break;
-                r[a] = 0;
-                --a;
-            }
-            if (a < 0) break;
-        }
+        for (int q = 0; q < nseg; ++q) S += hi[q] - lo[q];
         const int nch = int(std::max<int64_t>(1, (S + p->chunk - 1) / p->chunk));
         const int slot = nch > 1 ? int(slots) : -1;
         for (int c = 0; c < nch; ++c) items.push_back(GridItem{int(t), c, nch, slot});
@@ -336,16 +332,25 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
             hot.push_back(HotTile{int(t), slot, nch, 0});
             slots += nch;
         }
+        // gather work items: the tile's own bin in chunks of `ichunk`
+        const int b0 = start[size_t(t) << d], b1 = start[size_t(t + 1) << d];
+        for (int f = b0; f < b1; f += ichunk) iitems.push_back(InterpItem{int(t), f, std::min(ichunk, b1 - f), 0});
     }
-    dfree(p->bin_start);
+    dfree(p->sub_start);
     dfree(p->items);
+    dfree(p->iitems);
     dfree(p->hot);
-    HIP_TRY(upload(&p->bin_start, start), "upload bin offsets");
-    HIP_TRY(upload(&p->items, items), "upload work items");
-    HIP_TRY(upload(&p->hot, hot), "upload hot tiles");
+    HIP_TRY(upload(&p->sub_start, start), "upload bin offsets");
+    HIP_TRY(upload(&p->items, items), "upload gridding work items");
+    HIP_TRY(upload(&p->hot, hot), "upload split tiles");
     p->n_items = int64_t(items.size());
     p->n_hot = int64_t(hot.size());
     p->n_slots = slots;
+    p->n_iitems = 0;
+    if (p->staged_interp) {
+        HIP_TRY(upload(&p->iitems, iitems), "upload gather work items");
+        p->n_iitems = int64_t(iitems.size());
+    }
     return NUFFT_OK;
 }
 
@@ -480,6 +485,12 @@ int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s)
     a.grid_elems = p->grid_elems;
     a.grids = grids;
     a.y = y;
+    a.items = p->staged_interp ? p->iitems : nullptr;
+    a.n_items = p->n_iitems;
+    for (int ax = 0; ax < p->d; ++ax) {
+        a.T[ax] = p->T[ax];
+        a.nt[ax] = p->nt[ax];
+    }
     HIP_TRY(timed(p, kInterp, s, [&] { return launch_interp(a, s); }), "interpolation");
     return NUFFT_OK;
 }
@@ -489,7 +500,7 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.geo = p->geom();
     a.om_sorted = p->om_sorted;
     a.perm = p->perm;
-    a.bin_start = p->bin_start;
+    a.sub_start = p->sub_start;
     a.M = p->M;
     for (int ax = 0; ax < p->d; ++ax) {
         a.T[ax] = p->T[ax];
@@ -497,6 +508,10 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
         a.R[ax] = p->R[ax];
     }
     a.tile_cells = p->tile_cells;
+    a.seg_len = p->seg_len;
+    a.segs = p->segs;
+    a.group_lanes = p->group_lanes;
+    a.stage_floats = p->stage_floats;
     a.chunk = p->chunk;
     a.items = p->items;
     a.n_items = p->n_items;
@@ -537,7 +552,200 @@ int begin_call(nufft_plan_t plan, void *stream) {
 
 }  // namespace
 
+constexpr uint64_t kMultiMagic = 0x4e55464d554c5449ull;  // "NUFMULTI"
+constexpr int kMultiStreams = 4;
+
+struct GraphCache {
+    std::vector<const void *> in;
+    std::vector<void *> out;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct nufft_multi_s {
+    uint64_t magic = kMultiMagic;
+    int device = 0;
+    std::vector<nufft_plan_t> plans;
+    GraphCache fwd, adj;
+    std::vector<hipStream_t> streams;  // capture streams: [0] is the origin of the fork
+    std::vector<hipEvent_t> events;    // [0] fork, [1..] joins
+};
+
+namespace {
+
+std::set<const void *> g_multi_registry;
+
+int check_multi(nufft_multi_t m) {
+    if (!m) return fail(NUFFT_ERR_BAD_PLAN, "multi-plan handle is NULL");
+    std::lock_guard<std::mutex> lk(g_registry_mu);
+    if (!g_multi_registry.count(m) || m->magic != kMultiMagic)
+        return fail(NUFFT_ERR_BAD_PLAN, "multi-plan handle is not live");
+    return NUFFT_OK;
+}
+
+void drop_graph(GraphCache &gc) {
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+    gc.exec = nullptr;
+    gc.graph = nullptr;
+    gc.in.clear();
+    gc.out.clear();
+}
+
+void free_multi(nufft_multi_s *m);
+
+}  // namespace
+
+extern "C" int nufft_forward(nufft_plan_t plan, const void *x_dev, void *y_dev, void *stream);
+extern "C" int nufft_adjoint(nufft_plan_t plan, const void *y_dev, void *x_dev, void *stream);
+extern "C" int nufft_destroy(nufft_plan_t plan);
+
+namespace {
+
+void free_multi(nufft_multi_s *m) {
+    (void)hipSetDevice(m->device);
+    drop_graph(m->fwd);
+    drop_graph(m->adj);
+    for (auto st : m->streams) (void)hipStreamDestroy(st);
+    for (auto ev : m->events) (void)hipEventDestroy(ev);
+    m->streams.clear();
+    m->events.clear();
+    for (auto p : m->plans) (void)nufft_destroy(p);
+    m->plans.clear();
+}
+
+// Run all P transforms of one direction on `user`: capture them (forked over
+// the multi-plan's streams) into a graph the first time these pointers are
+// seen, then replay.
+int multi_run(nufft_multi_s *m, bool forward, const void *const *in, void *const *out, hipStream_t user) {
+    const size_t P = m->plans.size();
+    if (!in || !out) return fail(NUFFT_ERR_INVALID_ARG, "pointer arrays are NULL");
+    for (size_t p = 0; p < P; ++p)
+        if (!in[p] || !out[p]) return fail(NUFFT_ERR_INVALID_ARG, "pointer %zu is NULL", p);
+    HIP_TRY(hipSetDevice(m->device), "select device");
+    bool timing = false;
+    for (auto pl : m->plans) timing = timing || pl->timing;
+    if (timing) {  // per-kernel events cannot live in a graph: run the sequence directly
+        for (size_t p = 0; p < P; ++p) {
+            int st = forward ? nufft_forward(m->plans[p], in[p], out[p], user)
+                             : nufft_adjoint(m->plans[p], in[p], out[p], user);
+            if (st) return st;
+        }
+        return NUFFT_OK;
+    }
+    GraphCache &gc = forward ? m->fwd : m->adj;
+    bool hit = gc.exec && gc.in.size() == P;
+    for (size_t p = 0; hit && p < P; ++p) hit = gc.in[p] == in[p] && gc.out[p] == out[p];
+    if (!hit) {
+        drop_graph(gc);
+        hipStream_t origin = m->streams[0];
+        HIP_TRY(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal), "begin graph capture");
+        int st = NUFFT_OK;
+        hipError_t e = hipEventRecord(m->events[0], origin);
+        for (int k = 1; e == hipSuccess && k < kMultiStreams; ++k) e = hipStreamWaitEvent(m->streams[k], m->events[0], 0);
+        for (size_t p = 0; e == hipSuccess && st == NUFFT_OK && p < P; ++p) {
+            hipStream_t sp = m->streams[p % kMultiStreams];
+            st = forward ? nufft_forward(m->plans[p], in[p], out[p], sp) : nufft_adjoint(m->plans[p], in[p], out[p], sp);
+        }
+        for (int k = 1; e == hipSuccess && k < kMultiStreams; ++k) {
+            e = hipEventRecord(m->events[k], m->streams[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(origin, m->events[k], 0);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(origin, &graph);
+        if (st) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e != hipSuccess ? e : e2, "capture the multi-problem graph");
+        }
+        gc.graph = graph;
+        HIP_TRY(hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0), "instantiate the multi-problem graph");
+        gc.in.assign(in, in + P);
+        gc.out.assign(out, out + P);
+    }
+    HIP_TRY(hipGraphLaunch(gc.exec, user), "launch the multi-problem graph");
+    return NUFFT_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int nufft_multi_plan(int P, const nufft_problem_t *probs, void *stream, nufft_multi_t *out) {
+    if (!out) return fail(NUFFT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (P < 1 || P > 256 || !probs) return fail(NUFFT_ERR_INVALID_ARG, "P=%d must be in [1, 256]", P);
+    for (int p = 1; p < P; ++p)
+        if (probs[p].d != probs[0].d || probs[p].J != probs[0].J)
+            return fail(NUFFT_ERR_UNSUPPORTED, "problem %d has a different d or J", p);
+    nufft_multi_s *m = new (std::nothrow) nufft_multi_s();
+    if (!m) return fail(NUFFT_ERR_OOM, "host allocation failed");
+    auto bail = [&](int st) {
+        std::string msg = g_last_error;
+        free_multi(m);
+        delete m;
+        g_last_error = msg;
+        return st;
+    };
+    (void)hipGetDevice(&m->device);
+    for (int p = 0; p < P; ++p) {
+        const nufft_problem_t &pr = probs[p];
+        nufft_plan_t h = nullptr;
+        int st = nufft_plan(pr.d, pr.N, pr.K, pr.J, pr.M, pr.om, stream, &h);
+        if (st) return bail(st);
+        m->plans.push_back(h);
+        if (pr.C > 0) {
+            st = nufft_set_coils(h, pr.C, pr.coils);
+            if (st) return bail(st);
+        }
+    }
+    for (int k = 0; k < kMultiStreams; ++k) {
+        hipStream_t st;
+        hipEvent_t ev;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(hip_fail(e, "create capture stream"));
+        m->streams.push_back(st);
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return bail(hip_fail(e, "create capture event"));
+        m->events.push_back(ev);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_registry_mu);
+        g_multi_registry.insert(m);
+    }
+    *out = m;
+    return NUFFT_OK;
+}
+
+int nufft_multi_forward(nufft_multi_t m, const void *const *x_dev, void *const *y_dev, void *stream) {
+    int st = check_multi(m);
+    if (st) return st;
+    return multi_run(m, true, x_dev, y_dev, static_cast<hipStream_t>(stream));
+}
+
+int nufft_multi_adjoint(nufft_multi_t m, const void *const *y_dev, void *const *x_dev, void *stream) {
+    int st = check_multi(m);
+    if (st) return st;
+    return multi_run(m, false, y_dev, x_dev, static_cast<hipStream_t>(stream));
+}
+
+int nufft_multi_destroy(nufft_multi_t m) {
+    int st = check_multi(m);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_registry_mu);
+        g_multi_registry.erase(m);
+    }
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    free_multi(m);
+    m->magic = 0;
+    delete m;
+    return NUFFT_OK;
+}
 
 const char *nufft_status_string(int status) {
     switch (status) {
@@ -625,8 +833,10 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, cons
         p->K[a] = K[a];
     }
     // kernel, scaling and FFT constants per axis
-    const int targets[3][3] = {{256, 1, 1}, {32, 32, 1}, {8, 8, 16}};
-    const int need = (J - 1 + 1) / 2;
+    // tile edges: the last axis (one register row per lane in the gridding) at
+    // most 32 cells, the leading axes at most 64 rows in all
+    const int targets[3][3] = {{32, 1, 1}, {32, 16, 1}, {8, 8, 16}};
+    const int need = J - 1;
     p->tile_cells = 1;
     p->nbins = 1;
     for (int a = 0; a < d; ++a) {
@@ -635,7 +845,7 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, cons
         if (!radix_plan(int(K[a]), &p->rp[a])) return bail(fail(NUFFT_ERR_UNSUPPORTED, "no radix plan for K"));
         p->T[a] = choose_tile(K[a], targets[d - 1][a], std::max(1, need));
         p->nt[a] = int(K[a] / p->T[a]);
-        p->R[a] = std::min(p->nt[a], 1 + (J - 1 + p->T[a] - 1) / p->T[a]);
+        p->R[a] = p->nt[a] > 1 ? 2 : 1;
         p->tile_cells *= p->T[a];
         p->nbins *= p->nt[a];
         int st;
@@ -648,9 +858,45 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, cons
             return bail(st);
         }
     }
-    if (p->tile_cells > 8192) return bail(fail(NUFFT_ERR_UNSUPPORTED, "gridding tile too large"));
-    if (p->nbins >= (int64_t(1) << 30)) return bail(fail(NUFFT_ERR_UNSUPPORTED, "too many bins"));
-    p->chunk = d == 3 ? 512 : 2048;
+    {
+        // gridding: each lane accumulates LS cells of one tile row in registers;
+        // the smallest LS in {4, 8, 16} that keeps the tile within one
+        // wavefront (most lanes busy), else within the workgroup
+        const int L = p->T[d - 1];
+        const int rows = p->tile_cells / L;
+        int ls = 0;
+        for (int lim : {64, 256}) {
+            for (int cand : {4, 8, 16})
+                if (rows * ((L + cand - 1) / cand) <= lim) {
+                    ls = cand;
+                    break;
+                }
+            if (ls) break;
+        }
+        if (!ls) return bail(fail(NUFFT_ERR_UNSUPPORTED, "no gridding tile shape for this K and J"));
+        p->seg_len = ls;
+        p->segs = (L + ls - 1) / ls;
+        const int lanes = rows * p->segs;
+        p->group_lanes = 64 * ((lanes + 63) / 64);
+        const int B = p->group_lanes;
+        const int Lp = p->segs * ls;
+        const int staged = B * Lp + 2 * (B + 1) + (d - 1) * (B + 1) + (d - 1) * J * (B + 1);
+        p->stage_floats = std::max(staged, 2 * rows * Lp);
+        p->stage_floats = (p->stage_floats + 3) & ~3;  // keep every group's rows 16-byte aligned
+        if (int64_t(256 / p->group_lanes) * p->stage_floats * int64_t(sizeof(float)) > kLdsBudget)
+            return bail(fail(NUFFT_ERR_UNSUPPORTED, "gridding tile too large for LDS"));
+    }
+    {
+        int64_t region = sizeof(float2);
+        for (int a = 0; a < d; ++a) region *= p->T[a] + J - 1;
+        p->staged_interp = region <= kLdsBudget;
+    }
+    if ((p->nbins << d) >= (int64_t(1) << 30)) return bail(fail(NUFFT_ERR_UNSUPPORTED, "too many bins"));
+    p->chunk = d == 1 ? 2048 : 1024;
+    if (const char *env = std::getenv("NUFFT_GRID_CHUNK")) {  // tuning override
+        const int c = std::atoi(env);
+        if (c >= 64) p->chunk = c;
+    }
     // intermediate sizes of the FFT passes that land in the tmp buffer
     p->tmp_elems = 1;
     for (int pass = 0; pass < d - 1; ++pass) {

@@ -13,17 +13,18 @@
 //   k_interp       V, a gather of J^d taps per sample (Section 2.1
 //                  "Interpolation"), samples visited in grid-tile order.
 //   k_grid         V^H (gridding), output driven: a workgroup owns one grid tile,
-//                  accumulates the clipped windows of the samples that reach it
-//                  with LDS float atomics and writes the tile once, so no memset
-//                  and no global atomics are needed; crowded tiles are split into
-//                  chunks whose partial tiles k_reduce_partials sums in chunk
-//                  order.  The LDS atomics commit in arrival order, so the last
-//                  bits may differ from run to run.
+//                  lanes own rows of it in registers and walk the samples that
+//                  reach it (staged in LDS), so the tile is written once with
+//                  plain stores: no memset, no atomics, a fixed summation
+//                  order; crowded tiles are split into chunks whose partial
+//                  tiles k_reduce_partials sums in chunk order.
 //   k_grad         trajectory gradient through the derivative of the kernel.
 //
 // All arithmetic is float32 with float32 accumulation; window positions are
 // float64 (u = omega * K/(2 pi) as one rounded multiply).
 #include <hipcub/hipcub.hpp>
+
+#include <algorithm>
 
 #include "nufft_internal.h"
 
@@ -114,14 +115,17 @@ __device__ __forceinline__ void dft<8>(float2 *v) {
 }
 
 // ------------------------------------------------------------ Stockham passes in LDS
-// Element (line, q) of the tile lives at s[line * LS + q * ES].  STRIDED tiles
+// Element (line, q) of a tile lives at s[line * LS + q * ES].  STRIDED tiles
 // keep lines adjacent (ES = number of lines) so a wavefront's lanes walk
-// across lines; contiguous tiles keep each line contiguous (ES = 1).
-constexpr int kEPT = kFftTileElems / kFftThreads;  // complex elements per thread
+// across lines; contiguous tiles keep each line contiguous (ES = 1).  A tile
+// holds at most THREADS * kEPT complex elements; a thread handles up to
+// ceil(kEPT / R) butterflies of radix R per pass.  Twiddles e^{-2 pi i e / K}
+// are staged in LDS (tw) once per workgroup.
+constexpr int kEPT = 16;  // complex elements per thread
 
-template <int R, bool INV, bool STRIDED>
+template <int THREADS, int R, bool INV, bool STRIDED>
 __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS, int ES, int Ns,
-                                           const float2 *__restrict__ tw) {
+                                           const float2 *tw) {
     constexpr int NB = (kEPT + R - 1) / R;
     const int nbl = K / R;
     const int total = nlines * nbl;
@@ -129,7 +133,7 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
     int lidx[NB], jidx[NB];
 #pragma unroll
     for (int it = 0; it < NB; ++it) {
-        const int b = threadIdx.x + it * kFftThreads;
+        const int b = threadIdx.x + it * THREADS;
         lidx[it] = 0;
         jidx[it] = 0;
         if (b < total) {
@@ -152,7 +156,7 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
     const int span = K / (Ns * R);
 #pragma unroll
     for (int it = 0; it < NB; ++it) {
-        const int b = threadIdx.x + it * kFftThreads;
+        const int b = threadIdx.x + it * THREADS;
         if (b < total) {
             const int j = jidx[it];
             const int k = j % Ns;
@@ -181,30 +185,34 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
     __syncthreads();
 }
 
-template <bool INV, bool STRIDED>
-__device__ void lds_fft(float2 *s, int nlines, int K, int LS, int ES, const RadixPlan &rp,
-                        const float2 *__restrict__ tw) {
+template <int THREADS, bool INV, bool STRIDED>
+__device__ void lds_fft(float2 *s, int nlines, int K, int LS, int ES, const RadixPlan &rp, const float2 *tw) {
     int Ns = 1;
     for (int p = 0; p < rp.n; ++p) {
         const int R = rp.r[p];
         switch (R) {
-            case 8: radix_pass<8, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 4: radix_pass<4, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 2: radix_pass<2, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 3: radix_pass<3, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 5: radix_pass<5, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
+            case 8: radix_pass<THREADS, 8, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
+            case 4: radix_pass<THREADS, 4, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
+            case 2: radix_pass<THREADS, 2, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
+            case 3: radix_pass<THREADS, 3, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
+            case 5: radix_pass<THREADS, 5, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
             default: break;
         }
         Ns *= R;
     }
 }
 
+template <int THREADS>
+__device__ __forceinline__ void stage_twiddles(float2 *tw_lds, const float2 *__restrict__ tw, int K) {
+    for (int e = threadIdx.x; e < K; e += THREADS) tw_lds[e] = tw[e];
+}
+
 // Product of the scaling factors of the leading axes of image row r
-// (row-major over axes 0..d-2).
-__device__ __forceinline__ float row_scale(int d, const int *Nax, const float *const *scale, int64_t r) {
+// (row-major over axes 0..d-2), 32-bit index arithmetic.
+__device__ __forceinline__ float row_scale(int d, const int *Nax, const float *const *scale, int r) {
     float sc = 1.0f;
     for (int a = d - 2; a >= 0; --a) {
-        int64_t i = r % Nax[a];
+        const int i = r % Nax[a];
         r /= Nax[a];
         sc *= scale[a][i];
     }
@@ -221,39 +229,54 @@ __device__ __forceinline__ int src_row(int q, int N, int K) {
 }
 
 // ------------------------------------------------------------ FFT kernels
-__global__ __launch_bounds__(kFftThreads) void k_first_pass(FirstPassArgs a, int lines_per_wg) {
-    extern __shared__ float2 s[];
+// Dynamic LDS layout of every FFT kernel: [K twiddles][tile].
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lines_per_wg) {
+    extern __shared__ float2 lds[];
+    __shared__ float rsc[kMaxLinesPerWg];
+    __shared__ int xbase[kMaxLinesPerWg];
+    __shared__ int cbase[kMaxLinesPerWg];
     const int K = a.K, N = a.N;
+    float2 *tw = lds;
+    float2 *s = lds + K;
     const int64_t total = int64_t(a.B) * a.C * a.rows;
     const int64_t l0 = int64_t(blockIdx.x) * lines_per_wg;
     const int nl = int(min(int64_t(lines_per_wg), total - l0));
+    stage_twiddles<THREADS>(tw, a.tw, K);
+    if (threadIdx.x < nl) {
+        const int64_t l = l0 + threadIdx.x;
+        const int g = int(l / a.rows);
+        const int r = int(l - int64_t(g) * a.rows);
+        const int b = g / a.C;
+        const int c = g - b * a.C;
+        rsc[threadIdx.x] = row_scale(a.d, a.Nax, a.scale, r);
+        xbase[threadIdx.x] = (b * int(a.rows) + r) * N;
+        cbase[threadIdx.x] = (c * int(a.rows) + r) * N;
+    }
+    __syncthreads();
     const float *slast = a.scale[a.d - 1];
-    for (int e = threadIdx.x; e < nl * K; e += kFftThreads) {
+    for (int e = threadIdx.x; e < nl * K; e += THREADS) {
         const int lw = e / K, q = e - lw * K;
         float2 v = make_float2(0.f, 0.f);
         const int i = src_row(q, N, K);
         if (i >= 0) {
-            const int64_t l = l0 + lw;
-            const int64_t g = l / a.rows, r = l - g * a.rows;
-            const int64_t b = g / a.C;
-            const int64_t c = g - b * a.C;
-            v = a.x[(b * a.rows + r) * N + i];
-            const float sc = row_scale(a.d, a.Nax, a.scale, r) * slast[i];
-            v = cscale(v, sc);
-            if (a.coils) v = cmul(v, a.coils[(c * a.rows + r) * N + i]);
+            v = cscale(a.x[xbase[lw] + i], rsc[lw] * slast[i]);
+            if (a.coils) v = cmul(v, a.coils[cbase[lw] + i]);
         }
         s[e] = v;
     }
     __syncthreads();
-    lds_fft<false, false>(s, nl, K, K, 1, a.rp, a.tw);
+    lds_fft<THREADS, false, false>(s, nl, K, K, 1, a.rp, tw);
     float2 *out = a.out + l0 * K;
-    for (int e = threadIdx.x; e < nl * K; e += kFftThreads) out[e] = s[e];
+    for (int e = threadIdx.x; e < nl * K; e += THREADS) out[e] = s[e];
 }
 
-template <bool INV>
-__global__ __launch_bounds__(kFftThreads) void k_strided_pass(StridedPassArgs a, int W, int64_t ntc) {
-    extern __shared__ float2 s[];
+template <int THREADS, bool INV>
+__global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int W, int64_t ntc) {
+    extern __shared__ float2 lds[];
     const int K = a.K;
+    float2 *tw = lds;
+    float2 *s = lds + K;
     const int64_t bid = blockIdx.x;
     const int64_t ct = bid % ntc;
     const int64_t rest = bid / ntc;
@@ -263,7 +286,8 @@ __global__ __launch_bounds__(kFftThreads) void k_strided_pass(StridedPassArgs a,
     const int wv = int(min(int64_t(W), a.inner - c0));
     const float2 *in = a.in + ((g * a.outer + o) * a.Lin) * a.inner + c0;
     float2 *out = a.out + ((g * a.outer + o) * a.Lout) * a.inner + c0;
-    for (int e = threadIdx.x; e < K * W; e += kFftThreads) {
+    stage_twiddles<THREADS>(tw, a.tw, K);
+    for (int e = threadIdx.x; e < K * W; e += THREADS) {
         const int q = e / W, w = e - q * W;
         float2 v = make_float2(0.f, 0.f);
         if (w < wv) {
@@ -273,8 +297,8 @@ __global__ __launch_bounds__(kFftThreads) void k_strided_pass(StridedPassArgs a,
         s[e] = v;
     }
     __syncthreads();
-    lds_fft<INV, true>(s, W, K, 1, W, a.rp, a.tw);
-    for (int e = threadIdx.x; e < a.Lout * W; e += kFftThreads) {
+    lds_fft<THREADS, INV, true>(s, W, K, 1, W, a.rp, tw);
+    for (int e = threadIdx.x; e < a.Lout * W; e += THREADS) {
         const int i = e / W, w = e - i * W;
         if (w < wv) {
             const int q = (a.Lout == K) ? i : pad_pos(i, a.Lout, K);
@@ -283,53 +307,56 @@ __global__ __launch_bounds__(kFftThreads) void k_strided_pass(StridedPassArgs a,
     }
 }
 
-constexpr int kMaxOutPerThread = kFftTileElems / kFftThreads;
-
-__global__ __launch_bounds__(kFftThreads) void k_last_pass(LastPassArgs a, int rows_per_wg, int coils_per_round) {
-    extern __shared__ float2 s[];
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_per_wg, int coils_per_round) {
+    extern __shared__ float2 lds[];
+    __shared__ float rsc[kMaxLinesPerWg];
     const int K = a.K, N = a.N, C = a.C;
+    float2 *tw = lds;
+    float2 *s = lds + K;
+    // output accumulators (rows_per_wg * N of them) after the tile
+    float2 *acc = s + rows_per_wg * coils_per_round * K;
     const int64_t nrt = (a.rows + rows_per_wg - 1) / rows_per_wg;
     const int64_t b = blockIdx.x / nrt;
     const int64_t r0 = (blockIdx.x % nrt) * rows_per_wg;
     const int nr = int(min(int64_t(rows_per_wg), a.rows - r0));
-    float2 acc[kMaxOutPerThread];
-#pragma unroll
-    for (int it = 0; it < kMaxOutPerThread; ++it) acc[it] = make_float2(0.f, 0.f);
+    stage_twiddles<THREADS>(tw, a.tw, K);
+    if (threadIdx.x < nr) rsc[threadIdx.x] = row_scale(a.d, a.Nax, a.scale, int(r0) + threadIdx.x);
+    const bool one_round = coils_per_round >= C;
+    if (!one_round)
+        for (int e = threadIdx.x; e < nr * N; e += THREADS) acc[e] = make_float2(0.f, 0.f);
+    const float *slast = a.scale[a.d - 1];
     for (int c0 = 0; c0 < C; c0 += coils_per_round) {
         const int nc = min(coils_per_round, C - c0);
         const int nl = nr * nc;
-        for (int e = threadIdx.x; e < nl * K; e += kFftThreads) {
+        for (int e = threadIdx.x; e < nl * K; e += THREADS) {
             const int lw = e / K, q = e - lw * K;
             const int rr = lw / nc, cc = lw - rr * nc;
             s[e] = a.in[((b * C + c0 + cc) * a.rows + r0 + rr) * K + q];
         }
         __syncthreads();
-        lds_fft<true, false>(s, nl, K, K, 1, a.rp, a.tw);
-#pragma unroll
-        for (int it = 0; it < kMaxOutPerThread; ++it) {
-            const int e = threadIdx.x + it * kFftThreads;
-            if (e < nr * N) {
-                const int rr = e / N, i = e - rr * N;
-                const int q = pad_pos(i, N, K);
-                float2 v = make_float2(0.f, 0.f);
-                for (int cc = 0; cc < nc; ++cc) {
-                    float2 t = s[(rr * nc + cc) * K + q];
-                    if (a.coils) t = cmulcj(a.coils[(int64_t(c0 + cc) * a.rows + r0 + rr) * N + i], t);
-                    v = cadd(v, t);
-                }
-                acc[it] = cadd(acc[it], v);
+        lds_fft<THREADS, true, false>(s, nl, K, K, 1, a.rp, tw);
+        for (int e = threadIdx.x; e < nr * N; e += THREADS) {
+            const int rr = e / N, i = e - rr * N;
+            const int q = pad_pos(i, N, K);
+            float2 v = make_float2(0.f, 0.f);
+            for (int cc = 0; cc < nc; ++cc) {
+                float2 t = s[(rr * nc + cc) * K + q];
+                if (a.coils) t = cmulcj(a.coils[(int64_t(c0 + cc) * a.rows + r0 + rr) * N + i], t);
+                v = cadd(v, t);
+            }
+            if (one_round) {
+                a.x[(b * a.rows + r0 + rr) * N + i] = cscale(v, rsc[rr] * slast[i]);
+            } else {
+                acc[e] = cadd(acc[e], v);
             }
         }
         __syncthreads();
     }
-    const float *slast = a.scale[a.d - 1];
-#pragma unroll
-    for (int it = 0; it < kMaxOutPerThread; ++it) {
-        const int e = threadIdx.x + it * kFftThreads;
-        if (e < nr * N) {
+    if (!one_round) {
+        for (int e = threadIdx.x; e < nr * N; e += THREADS) {
             const int rr = e / N, i = e - rr * N;
-            const float sc = row_scale(a.d, a.Nax, a.scale, r0 + rr) * slast[i];
-            a.x[(b * a.rows + r0 + rr) * N + i] = cscale(acc[it], sc);
+            a.x[(b * a.rows + r0 + rr) * N + i] = cscale(acc[e], rsc[rr] * slast[i]);
         }
     }
 }
@@ -366,9 +393,124 @@ __device__ __forceinline__ void window_weights(const float *__restrict__ coef, i
     }
 }
 
+// ------------------------------------------------------------ work distribution
+// Workgroup b of n runs item xcd_item(b, n): the hardware deals consecutive
+// workgroups round-robin over the 8 XCDs, so this hands each XCD a contiguous
+// run of items (neighbouring tiles), whose shared halos and neighbour samples
+// then stay in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
+    const int64_t x = b & 7, idx = b >> 3;
+    const int64_t q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + idx;
+}
+
 // ------------------------------------------------------------ V (gather)
+// One workgroup per (bin, chunk): the tile and its J-1 halo of the grid are
+// staged in LDS once, then every sample of the chunk (window base inside the
+// tile) reads its J^d taps from LDS.
 template <int J, int DIM>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
+    extern __shared__ float2 reg[];
+    const InterpItem it = a.items[xcd_item(blockIdx.x, gridDim.x)];
+    int tc[DIM], base[DIM], E[DIM];
+    {
+        int t = it.bin;
+#pragma unroll
+        for (int ax = DIM - 1; ax >= 0; --ax) {
+            tc[ax] = t % a.nt[ax];
+            t /= a.nt[ax];
+        }
+    }
+    int region = 1;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        base[ax] = tc[ax] * a.T[ax];
+        E[ax] = a.T[ax] + J - 1;
+        region *= E[ax];
+    }
+    constexpr int SPT = kInterpSamplesPerThread;
+    float w[SPT][DIM][J];
+    int off[SPT];
+    bool valid[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int s = threadIdx.x + k * 256;
+        valid[k] = s < it.count;
+        off[k] = 0;
+        if (valid[k]) {
+            const int64_t i = it.start + s;
+            int o = 0;
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                int kk[J];
+                const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk);
+                window_weights<J>(a.geo.coef[ax], a.geo.deg[ax], f, w[k][ax]);
+                o = o * E[ax] + (kk[0] - base[ax]);
+            }
+            off[k] = o;
+        }
+    }
+    for (int g = 0; g < a.grids; ++g) {
+        const float2 *G = a.G + int64_t(g) * a.grid_elems;
+        __syncthreads();
+        for (int e = threadIdx.x; e < region; e += 256) {
+            int rem = e;
+            int64_t idx = 0;
+            int l[DIM];
+#pragma unroll
+            for (int ax = DIM - 1; ax >= 0; --ax) {
+                l[ax] = rem % E[ax];
+                rem /= E[ax];
+            }
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                int k = base[ax] + l[ax];
+                if (k >= a.geo.K[ax]) k -= a.geo.K[ax];
+                idx = idx * a.geo.K[ax] + k;
+            }
+            reg[e] = G[idx];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            if (!valid[k]) continue;
+            float2 acc = make_float2(0.f, 0.f);
+            const float2 *r0 = reg + off[k];
+            if constexpr (DIM == 1) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) acc = cadd(acc, cscale(r0[j], w[k][0][j]));
+            } else if constexpr (DIM == 2) {
+#pragma unroll
+                for (int j0 = 0; j0 < J; ++j0) {
+                    const float2 *row = r0 + j0 * E[1];
+                    float2 rs = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int j1 = 0; j1 < J; ++j1) rs = cadd(rs, cscale(row[j1], w[k][1][j1]));
+                    acc = cadd(acc, cscale(rs, w[k][0][j0]));
+                }
+            } else {
+                for (int j0 = 0; j0 < J; ++j0) {
+                    float2 ps = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int j1 = 0; j1 < J; ++j1) {
+                        const float2 *row = r0 + (j0 * E[1] + j1) * E[2];
+                        float2 rs = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int j2 = 0; j2 < J; ++j2) rs = cadd(rs, cscale(row[j2], w[k][2][j2]));
+                        ps = cadd(ps, cscale(rs, w[k][1][j1]));
+                    }
+                    acc = cadd(acc, cscale(ps, w[k][0][j0]));
+                }
+            }
+            a.y[int64_t(g) * a.M + a.perm[it.start + threadIdx.x + k * 256]] = acc;
+        }
+    }
+}
+
+// Gather straight from the grid (L1/L2), one thread per sorted sample: used
+// when the tile-plus-halo region does not fit the LDS budget.
+template <int J, int DIM>
+__global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.M) return;
     float w[DIM][J];
@@ -415,20 +557,49 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
 }
 
 // ------------------------------------------------------------ V^H (output-driven gridding)
-template <int J, int DIM>
-__global__ __launch_bounds__(256) void k_grid(GridArgs a) {
-    extern __shared__ float acc_lds[];
-    float *are = acc_lds;
-    float *aim = acc_lds + a.tile_cells;
-    __shared__ int seg_start[kMaxNeighbors];
+// One workgroup per (tile, chunk).  The samples that reach the tile are the
+// tile's own bin plus, from each lower neighbour bin, only the sub-bins whose
+// windows cross into this tile (tile_segments).
+//
+// No atomics: the tile's rows (leading coordinates) are cut into segments of
+// LS cells along the last axis, one segment per lane, held in registers.
+// Samples are staged in LDS in batches: window offsets along the leading
+// axes, their per-axis weights, the value, and the last-axis weights already
+// expanded into a zero-padded row of the tile (so the inner loop needs no
+// tap index and no branch).  Every lane of a group then walks the group's
+// batch and adds LS weighted values per sample.  Lane groups split the
+// samples; their register tiles are summed through LDS at the end in group
+// order, so the result does not depend on scheduling.
+constexpr int kGridThreads = 256;
+
+template <int DIM, int LS>
+__global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
+    extern __shared__ float4 stage_mem[];  // float4: 16-byte aligned rows for the vector reads
+    float *stage = reinterpret_cast<float *>(stage_mem);
+    __shared__ int seg_lo[kMaxNeighbors];
+    __shared__ int seg_hi[kMaxNeighbors];
     __shared__ int seg_pre[kMaxNeighbors + 1];
     __shared__ int nseg_s;
-    const GridItem it = a.items[blockIdx.x];
+    const GridItem it = a.items[xcd_item(blockIdx.x, gridDim.x)];
     const int g = blockIdx.y;
-    for (int e = threadIdx.x; e < a.tile_cells; e += blockDim.x) {
-        are[e] = 0.f;
-        aim[e] = 0.f;
-    }
+    const int J = a.geo.J;
+    const int L = a.T[DIM - 1];           // cells per tile row
+    const int S = a.segs;                 // segments per row
+    const int Lp = S * LS;                // padded row length
+    const int lead = a.tile_cells / L;    // rows of the tile
+    const int gsize = a.group_lanes;      // lanes per sample group (multiple of 64, >= lead * S)
+    const int ngroups = kGridThreads / gsize;
+    const int grp = threadIdx.x / gsize;
+    const int lane = threadIdx.x - grp * gsize;
+    const int B = gsize;                  // samples per batch and group
+    const int BP = B + 1;
+    // staged arrays of this group
+    float *gbase = stage + grp * a.stage_floats;
+    float *wrow = gbase;                              // [B][Lp] last-axis weights on the row
+    float *sv = wrow + B * Lp;                        // [2][BP] value
+    int *so = reinterpret_cast<int *>(sv + 2 * BP);   // [DIM-1][BP] leading first-tap offsets
+    float *sw = sv + 2 * BP + (DIM - 1) * BP;         // [DIM-1][J][BP] leading weights
+
     int tc[DIM];
     {
         int t = it.tile;
@@ -439,30 +610,11 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs a) {
         }
     }
     if (threadIdx.x == 0) {
-        int n = 0, pre = 0;
-        int r[DIM];
-#pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) r[ax] = 0;
-        while (true) {
-            int bin = 0;
-#pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) {
-                int bt = tc[ax] - r[ax];
-                if (bt < 0) bt += a.nt[ax];
-                bin = bin * a.nt[ax] + bt;
-            }
-            const int s0 = a.bin_start[bin], s1 = a.bin_start[bin + 1];
-            seg_start[n] = s0;
-            seg_pre[n] = pre;
-            pre += s1 - s0;
-            ++n;
-            int ax = DIM - 1;
-            while (ax >= 0) {
-                if (++r[ax] < a.R[ax]) break;
-                r[ax] = 0;
-                --ax;
-            }
-            if (ax < 0) break;
+        const int n = tile_segments(DIM, tc, a.nt, a.R, a.sub_start, seg_lo, seg_hi);
+        int pre = 0;
+        for (int q = 0; q < n; ++q) {
+            seg_pre[q] = pre;
+            pre += seg_hi[q] - seg_lo[q];
         }
         seg_pre[n] = pre;
         nseg_s = n;
@@ -471,103 +623,162 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs a) {
     const int nseg = nseg_s;
     const int total = seg_pre[nseg];
     const int f0 = it.chunk * a.chunk;
-    const int f1 = min(total, f0 + a.chunk);
-    const float2 *y = a.y + int64_t(g) * a.M;
+    const int n = min(total, f0 + a.chunk) - f0;
     int base[DIM];
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) base[ax] = tc[ax] * a.T[ax];
-    for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
-        int n = 0;
-        while (n + 1 < nseg && seg_pre[n + 1] <= f) ++n;
-        const int64_t i = seg_start[n] + (f - seg_pre[n]);
-        int loc[DIM][J];
-        float fo[DIM];
-        bool hit = true;
+    // this lane's segment: row (leading coordinates) and first cell
+    const int row = lane / S;
+    const int cseg = (lane - row * S) * LS;
+    int lc[DIM];
+    {
+        int r = row;
 #pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) {
-            int kk[J];
-            fo[ax] = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk);
-            bool any = false;
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const int l = kk[j] - base[ax];
-                const bool in = (l >= 0) && (l < a.T[ax]);
-                loc[ax][j] = in ? l : -1;
-                any = any || in;
-            }
-            hit = hit && any;
+        for (int ax = DIM - 2; ax >= 0; --ax) {
+            lc[ax] = r % a.T[ax];
+            r /= a.T[ax];
         }
-        if (!hit) continue;
-        float w[DIM][J];
+        lc[DIM - 1] = cseg;
+    }
+    const bool row_ok = row < lead;
+    const float2 *y = a.y + int64_t(g) * a.M;
+    float2 acc[LS];
 #pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) window_weights<J>(a.geo.coef[ax], a.geo.deg[ax], fo[ax], w[ax]);
-        const float2 v = y[a.perm[i]];
-        if constexpr (DIM == 1) {
+    for (int c = 0; c < LS; ++c) acc[c] = make_float2(0.f, 0.f);
+
+    const int per_iter = B * ngroups;
+    for (int b0 = 0; b0 < n; b0 += per_iter) {
+        // ---- stage one batch per group: lane `lane` stages sample b0 + grp*B + lane
+        const int s_idx = b0 + grp * B + lane;
+        if (s_idx < n) {
+            const int f = f0 + s_idx;
+            int sg = 0;
+            while (sg + 1 < nseg && seg_pre[sg + 1] <= f) ++sg;
+            const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
+            float *wr = wrow + lane * Lp;
+            for (int c = 0; c < Lp; ++c) wr[c] = 0.f;
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                if (loc[0][j] < 0) continue;
-                atomicAdd(&are[loc[0][j]], w[0][j] * v.x);
-                atomicAdd(&aim[loc[0][j]], w[0][j] * v.y);
-            }
-        } else if constexpr (DIM == 2) {
-            const int T1 = a.T[1];
-#pragma unroll
-            for (int j0 = 0; j0 < J; ++j0) {
-                if (loc[0][j0] < 0) continue;
-                const float2 v0 = cscale(v, w[0][j0]);
-                const int rb = loc[0][j0] * T1;
-#pragma unroll
-                for (int j1 = 0; j1 < J; ++j1) {
-                    if (loc[1][j1] < 0) continue;
-                    atomicAdd(&are[rb + loc[1][j1]], w[1][j1] * v0.x);
-                    atomicAdd(&aim[rb + loc[1][j1]], w[1][j1] * v0.y);
-                }
-            }
-        } else {
-            const int T1 = a.T[1], T2 = a.T[2];
-            for (int j0 = 0; j0 < J; ++j0) {
-                if (loc[0][j0] < 0) continue;
-                const float2 v0 = cscale(v, w[0][j0]);
-#pragma unroll
-                for (int j1 = 0; j1 < J; ++j1) {
-                    if (loc[1][j1] < 0) continue;
-                    const float2 v1 = cscale(v0, w[1][j1]);
-                    const int rb = (loc[0][j0] * T1 + loc[1][j1]) * T2;
-#pragma unroll
-                    for (int j2 = 0; j2 < J; ++j2) {
-                        if (loc[2][j2] < 0) continue;
-                        atomicAdd(&are[rb + loc[2][j2]], w[2][j2] * v1.x);
-                        atomicAdd(&aim[rb + loc[2][j2]], w[2][j2] * v1.y);
+            for (int ax = 0; ax < DIM; ++ax) {
+                const double u = __dmul_rn(double(a.om_sorted[i * DIM + ax]), a.geo.C[ax]);
+                const double k0 = floor(u - 0.5 * J) + 1.0;
+                const float fr = float(u - k0 - (0.5 * J - 1.0));
+                const int K = a.geo.K[ax];
+                long long kw = static_cast<long long>(k0) % K;
+                if (kw < 0) kw += K;
+                int o = int(kw) - base[ax];
+                if (a.nt[ax] > 1 && o >= a.T[ax]) o -= K;  // window wrapping in from the top
+                const float z = 2.0f * fr - 1.0f;
+                const float *coef = a.geo.coef[ax];
+                const int deg = a.geo.deg[ax];
+                for (int j = 0; j < J; ++j) {
+                    const float *cj = coef + j * (deg + 1);
+                    float v = cj[deg];
+                    for (int q = deg - 1; q >= 0; --q) v = fmaf(v, z, cj[q]);
+                    if (ax < DIM - 1) {
+                        sw[(ax * J + j) * BP + lane] = v;
+                    } else {
+                        int c = o + j;
+                        if (a.nt[ax] == 1 && c >= K) c -= K;
+                        if (c >= 0 && c < L) wr[c] = v;
                     }
                 }
+                if (ax < DIM - 1) so[ax * BP + lane] = o;
+            }
+            const float2 v = y[a.perm[i]];
+            sv[lane] = v.x;
+            sv[BP + lane] = v.y;
+        }
+        __syncthreads();
+        // ---- every lane of the group walks the group's batch
+        const int nb = min(B, n - (b0 + grp * B));
+#pragma unroll 2
+        for (int s = 0; s < nb; ++s) {
+            float wl = row_ok ? 1.f : 0.f;
+#pragma unroll
+            for (int ax = 0; ax < DIM - 1; ++ax) {
+                int j = lc[ax] - so[ax * BP + s];
+                if (a.nt[ax] == 1 && j < 0) j += a.geo.K[ax];
+                const bool in = (j >= 0) && (j < J);
+                const float w = sw[(ax * J + (in ? j : 0)) * BP + s];
+                wl = in ? wl * w : 0.f;
+            }
+            const float vr = sv[s] * wl, vi = sv[BP + s] * wl;
+            const float4 *wr4 = reinterpret_cast<const float4 *>(wrow + s * Lp + cseg);
+#pragma unroll
+            for (int q = 0; q < LS / 4; ++q) {
+                const float4 w = wr4[q];
+                acc[4 * q + 0].x = fmaf(w.x, vr, acc[4 * q + 0].x);
+                acc[4 * q + 0].y = fmaf(w.x, vi, acc[4 * q + 0].y);
+                acc[4 * q + 1].x = fmaf(w.y, vr, acc[4 * q + 1].x);
+                acc[4 * q + 1].y = fmaf(w.y, vi, acc[4 * q + 1].y);
+                acc[4 * q + 2].x = fmaf(w.z, vr, acc[4 * q + 2].x);
+                acc[4 * q + 2].y = fmaf(w.z, vi, acc[4 * q + 2].y);
+                acc[4 * q + 3].x = fmaf(w.w, vr, acc[4 * q + 3].x);
+                acc[4 * q + 3].y = fmaf(w.w, vi, acc[4 * q + 3].y);
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
-    if (it.nchunks == 1) {
-        float2 *h = a.h + int64_t(g) * a.grid_elems;
-        for (int e = threadIdx.x; e < a.tile_cells; e += blockDim.x) {
-            int rem = e;
-            int64_t idx = 0;
-            int l[DIM];
+    // ---- combine the groups' register tiles (group order), write the tile
+    float2 *red = reinterpret_cast<float2 *>(stage);  // [ngroups][lead][Lp], reuses the staging LDS
+    const bool seg_ok = row_ok;
+    if (ngroups > 1) {
+        if (seg_ok) {
 #pragma unroll
-            for (int ax = DIM - 1; ax >= 0; --ax) {
-                l[ax] = rem % a.T[ax];
-                rem /= a.T[ax];
+            for (int c = 0; c < LS; ++c) red[(grp * lead + row) * Lp + cseg + c] = acc[c];
+        }
+        __syncthreads();
+    }
+    const bool to_partial = it.nchunks > 1;
+    float2 *dst = to_partial ? a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells
+                             : a.h + int64_t(g) * a.grid_elems;
+    if (ngroups == 1) {
+        if (seg_ok) {
+            int64_t idx;
+            if (to_partial) {
+                idx = int64_t(row) * L + cseg;
+            } else {
+                idx = 0;
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) idx = idx * a.geo.K[ax] + base[ax] + lc[ax];
             }
 #pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) idx = idx * a.geo.K[ax] + base[ax] + l[ax];
-            h[idx] = make_float2(are[e], aim[e]);
+            for (int c = 0; c < LS; ++c)
+                if (cseg + c < L) dst[idx + c] = acc[c];
         }
     } else {
-        float2 *p = a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells;
-        for (int e = threadIdx.x; e < a.tile_cells; e += blockDim.x) p[e] = make_float2(are[e], aim[e]);
+        for (int e = threadIdx.x; e < lead * L; e += kGridThreads) {
+            const int r = e / L, c = e - r * L;
+            float2 sum = red[r * Lp + c];
+            for (int q = 1; q < ngroups; ++q) sum = cadd(sum, red[(q * lead + r) * Lp + c]);
+            int64_t idx;
+            if (to_partial) {
+                idx = e;
+            } else {
+                int rr = r;
+                int l[DIM];
+                l[DIM - 1] = c;
+#pragma unroll
+                for (int ax = DIM - 2; ax >= 0; --ax) {
+                    l[ax] = rr % a.T[ax];
+                    rr /= a.T[ax];
+                }
+                idx = 0;
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) idx = idx * a.geo.K[ax] + base[ax] + l[ax];
+            }
+            dst[idx] = sum;
+        }
     }
 }
 
+// Sums the partial tiles of every split tile in chunk order; one workgroup per
+// (tile, 256 cells, grid).
 __global__ __launch_bounds__(256) void k_reduce_partials(ReduceArgs a) {
     const HotTile ht = a.hot[blockIdx.x];
-    const int g = blockIdx.y;
+    const int g = blockIdx.z;
+    const int e = blockIdx.y * 256 + threadIdx.x;
+    if (e >= a.tile_cells) return;
     int tc[kMaxDim];
     {
         int t = ht.tile;
@@ -576,21 +787,18 @@ __global__ __launch_bounds__(256) void k_reduce_partials(ReduceArgs a) {
             t /= a.nt[ax];
         }
     }
-    const float2 *p = a.partials + (int64_t(g) * a.n_slots + ht.slot) * a.tile_cells;
-    float2 *h = a.h + int64_t(g) * a.grid_elems;
-    for (int e = threadIdx.x; e < a.tile_cells; e += blockDim.x) {
-        float2 acc = make_float2(0.f, 0.f);
-        for (int c = 0; c < ht.nchunks; ++c) acc = cadd(acc, p[int64_t(c) * a.tile_cells + e]);
-        int rem = e;
-        int l[kMaxDim];
-        for (int ax = a.d - 1; ax >= 0; --ax) {
-            l[ax] = rem % a.T[ax];
-            rem /= a.T[ax];
-        }
-        int64_t idx = 0;
-        for (int ax = 0; ax < a.d; ++ax) idx = idx * a.K[ax] + tc[ax] * a.T[ax] + l[ax];
-        h[idx] = acc;
+    const float2 *p = a.partials + (int64_t(g) * a.n_slots + ht.slot) * a.tile_cells + e;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int c = 0; c < ht.nchunks; ++c) acc = cadd(acc, p[int64_t(c) * a.tile_cells]);
+    int rem = e;
+    int l[kMaxDim];
+    for (int ax = a.d - 1; ax >= 0; --ax) {
+        l[ax] = rem % a.T[ax];
+        rem /= a.T[ax];
     }
+    int64_t idx = 0;
+    for (int ax = 0; ax < a.d; ++ax) idx = idx * a.K[ax] + tc[ax] * a.T[ax] + l[ax];
+    a.h[int64_t(g) * a.grid_elems + idx] = acc;
 }
 
 // ------------------------------------------------------------ trajectory gradient
@@ -665,10 +873,12 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs a) {
 }
 
 // ------------------------------------------------------------ plan-time binning
+// key = (tile of the first tap) * 2^d + crossing code, bit a set when the
+// window leaves the tile through its upper face along axis a.
 __global__ __launch_bounds__(256) void k_bin_keys(BinArgs a) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.M) return;
-    int key = 0;
+    int key = 0, code = 0;
     bool bad = false;
     for (int ax = 0; ax < a.d; ++ax) {
         const float om = a.om[i * a.d + ax];
@@ -684,10 +894,12 @@ __global__ __launch_bounds__(256) void k_bin_keys(BinArgs a) {
                 long long kw = static_cast<long long>(k0) % a.K[ax];
                 if (kw < 0) kw += a.K[ax];
                 tile = int(kw) / a.T[ax];
+                if (a.nt[ax] > 1 && int(kw) - tile * a.T[ax] + a.J - 1 >= a.T[ax]) code |= 1 << ax;
             }
         }
         key = key * a.nt[ax] + tile;
     }
+    key = (key << a.d) | code;
     if (bad) atomicOr(a.flag, 1);
     a.keys[i] = key;
     atomicAdd(&a.counts[key], 1);
@@ -748,18 +960,15 @@ template <int J, int DIM>
 struct InterpLaunch {
     static hipError_t go(const InterpArgs &a, hipStream_t s) {
         if (a.M == 0) return hipSuccess;
-        const int64_t blocks = (a.M + 255) / 256;
-        hipLaunchKernelGGL((k_interp<J, DIM>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
-        return hipGetLastError();
-    }
-};
-
-template <int J, int DIM>
-struct GridLaunch {
-    static hipError_t go(const GridArgs &a, hipStream_t s) {
-        if (a.n_items == 0) return hipSuccess;
-        const size_t lds = size_t(a.tile_cells) * 2 * sizeof(float);
-        hipLaunchKernelGGL((k_grid<J, DIM>), dim3(unsigned(a.n_items), unsigned(a.grids)), dim3(256), lds, s, a);
+        if (a.items) {
+            if (a.n_items == 0) return hipSuccess;
+            size_t region = sizeof(float2);
+            for (int ax = 0; ax < DIM; ++ax) region *= size_t(a.T[ax] + J - 1);
+            hipLaunchKernelGGL((k_interp<J, DIM>), dim3(unsigned(a.n_items)), dim3(256), region, s, a);
+        } else {
+            const int64_t blocks = (a.M + 255) / 256;
+            hipLaunchKernelGGL((k_interp_direct<J, DIM>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+        }
         return hipGetLastError();
     }
 };
@@ -774,65 +983,152 @@ struct GradLaunch {
     }
 };
 
+// FFT tile sizes: a tile holds up to THREADS * kEPT elements.  The host takes
+// the largest tile that still leaves about kFftTargetGroups workgroups (small
+// transforms spread over the whole chip), then the smallest block that holds
+// it.
+constexpr int64_t kFftTargetGroups = 1024;
+
+template <template <int> class L, class A>
+hipError_t fft_dispatch(int threads, const A &a, hipStream_t s, int p0, int64_t p1, size_t lds, unsigned blocks) {
+    switch (threads) {
+        case 64: return L<64>::go(a, s, p0, p1, lds, blocks);
+        case 128: return L<128>::go(a, s, p0, p1, lds, blocks);
+        case 256: return L<256>::go(a, s, p0, p1, lds, blocks);
+        default: return L<512>::go(a, s, p0, p1, lds, blocks);
+    }
+}
+
+int threads_for(int elems) {
+    int t = 64;
+    while (t < 512 && t * kEPT < elems) t *= 2;
+    return t;
+}
+
+template <int T>
+struct FirstGo {
+    static hipError_t go(const FirstPassArgs &a, hipStream_t s, int lpw, int64_t, size_t lds, unsigned blocks) {
+        hipLaunchKernelGGL(k_first_pass<T>, dim3(blocks), dim3(T), lds, s, a, lpw);
+        return hipGetLastError();
+    }
+};
+
+template <int T>
+struct StridedGoF {
+    static hipError_t go(const StridedPassArgs &a, hipStream_t s, int W, int64_t ntc, size_t lds, unsigned blocks) {
+        hipLaunchKernelGGL((k_strided_pass<T, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+        return hipGetLastError();
+    }
+};
+
+template <int T>
+struct StridedGoI {
+    static hipError_t go(const StridedPassArgs &a, hipStream_t s, int W, int64_t ntc, size_t lds, unsigned blocks) {
+        hipLaunchKernelGGL((k_strided_pass<T, true>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+        return hipGetLastError();
+    }
+};
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s) {
     const int64_t total = int64_t(a.B) * a.C * a.rows;
     if (total == 0) return hipSuccess;
-    const int lpw = max(1, kFftTileElems / a.K);
+    const int cap = kFftTileElems / a.K;  // lines that fit the largest tile
+    int lpw = int(std::min<int64_t>(std::max<int64_t>(1, total / kFftTargetGroups), std::min(cap, kMaxLinesPerWg)));
+    lpw = std::max(1, lpw);
+    const int threads = threads_for(lpw * a.K);
     const int64_t blocks = (total + lpw - 1) / lpw;
-    const size_t lds = size_t(lpw) * a.K * sizeof(float2);
-    hipLaunchKernelGGL(k_first_pass, dim3(unsigned(blocks)), dim3(kFftThreads), lds, s, a, lpw);
-    return hipGetLastError();
+    const size_t lds = size_t(lpw + 1) * a.K * sizeof(float2);
+    return fft_dispatch<FirstGo>(threads, a, s, lpw, 0, lds, unsigned(blocks));
 }
 
 hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s) {
-    if (a.grids * a.outer * a.inner == 0) return hipSuccess;
-    int W = max(1, kFftTileElems / a.K);
-    if (int64_t(W) > a.inner) W = int(a.inner);
+    const int64_t columns = a.grids * a.outer * a.inner;
+    if (columns == 0) return hipSuccess;
+    const int cap = std::max(1, kFftTileElems / a.K);
+    // columns per tile: at least 4 adjacent (32-byte rows), fewer only for narrow arrays
+    int64_t W = std::max<int64_t>(4, columns / kFftTargetGroups);
+    W = std::min<int64_t>(W, cap);
+    W = std::min<int64_t>(W, a.inner);
+    W = std::max<int64_t>(W, 1);
     const int64_t ntc = (a.inner + W - 1) / W;
     const int64_t blocks = ntc * a.outer * a.grids;
-    const size_t lds = size_t(W) * a.K * sizeof(float2);
-    if (a.inverse)
-        hipLaunchKernelGGL(k_strided_pass<true>, dim3(unsigned(blocks)), dim3(kFftThreads), lds, s, a, W, ntc);
-    else
-        hipLaunchKernelGGL(k_strided_pass<false>, dim3(unsigned(blocks)), dim3(kFftThreads), lds, s, a, W, ntc);
-    return hipGetLastError();
+    const int threads = threads_for(int(W) * a.K);
+    const size_t lds = size_t(W + 1) * a.K * sizeof(float2);
+    if (a.inverse) return fft_dispatch<StridedGoI>(threads, a, s, int(W), ntc, lds, unsigned(blocks));
+    return fft_dispatch<StridedGoF>(threads, a, s, int(W), ntc, lds, unsigned(blocks));
 }
 
+namespace {
+template <int T>
+struct LastGo {
+    static hipError_t go(const LastPassArgs &a, hipStream_t s, int rpw, int64_t cpr, size_t lds, unsigned blocks) {
+        hipLaunchKernelGGL(k_last_pass<T>, dim3(blocks), dim3(T), lds, s, a, rpw, int(cpr));
+        return hipGetLastError();
+    }
+};
+}  // namespace
+
 hipError_t launch_last_pass(const LastPassArgs &a, hipStream_t s) {
-    if (int64_t(a.B) * a.rows == 0) return hipSuccess;
+    const int64_t total_rows = int64_t(a.B) * a.rows;
+    if (total_rows == 0) return hipSuccess;
     int rows_per_wg, coils_per_round;
     if (a.C * a.K <= kFftTileElems) {
         coils_per_round = a.C;
-        rows_per_wg = max(1, kFftTileElems / (a.C * a.K));
+        const int cap = std::min(kFftTileElems / (a.C * a.K), kMaxLinesPerWg);
+        rows_per_wg = int(std::min<int64_t>(std::max<int64_t>(1, total_rows / kFftTargetGroups), cap));
     } else {
         rows_per_wg = 1;
-        coils_per_round = max(1, kFftTileElems / a.K);
+        coils_per_round = std::max(1, kFftTileElems / a.K);
     }
-    // at most kMaxOutPerThread outputs per thread
-    while (rows_per_wg > 1 && rows_per_wg * a.N > kMaxOutPerThread * kFftThreads) --rows_per_wg;
     if (int64_t(rows_per_wg) > a.rows) rows_per_wg = int(a.rows);
+    rows_per_wg = std::max(1, rows_per_wg);
+    const int threads = threads_for(rows_per_wg * coils_per_round * a.K);
     const int64_t nrt = (a.rows + rows_per_wg - 1) / rows_per_wg;
     const int64_t blocks = nrt * a.B;
-    const size_t lds = size_t(rows_per_wg) * coils_per_round * a.K * sizeof(float2);
-    hipLaunchKernelGGL(k_last_pass, dim3(unsigned(blocks)), dim3(kFftThreads), lds, s, a, rows_per_wg,
-                       coils_per_round);
-    return hipGetLastError();
+    const bool one_round = coils_per_round >= a.C;
+    const size_t lds = (size_t(a.K) + size_t(rows_per_wg) * coils_per_round * a.K +
+                        (one_round ? 0 : size_t(rows_per_wg) * a.N)) * sizeof(float2);
+    return fft_dispatch<LastGo>(threads, a, s, rows_per_wg, coils_per_round, lds, unsigned(blocks));
 }
 
 hipError_t launch_interp(const InterpArgs &a, hipStream_t s) {
     return dispatch_jd<InterpLaunch>(a.geo.J, a.geo.d, a, s);
 }
 
+template <int DIM, int LS>
+hipError_t launch_grid_t(const GridArgs &a, hipStream_t s) {
+    const size_t lds = size_t(kGridThreads / a.group_lanes) * a.stage_floats * sizeof(float);
+    hipLaunchKernelGGL((k_grid<DIM, LS>), dim3(unsigned(a.n_items), unsigned(a.grids)), dim3(kGridThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t launch_grid_d(const GridArgs &a, hipStream_t s) {
+    switch (a.seg_len) {
+        case 4: return launch_grid_t<DIM, 4>(a, s);
+        case 8: return launch_grid_t<DIM, 8>(a, s);
+        case 16: return launch_grid_t<DIM, 16>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_grid(const GridArgs &a, hipStream_t s) {
-    return dispatch_jd<GridLaunch>(a.geo.J, a.geo.d, a, s);
+    if (a.n_items == 0) return hipSuccess;
+    switch (a.geo.d) {
+        case 1: return launch_grid_d<1>(a, s);
+        case 2: return launch_grid_d<2>(a, s);
+        case 3: return launch_grid_d<3>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_reduce_partials(const ReduceArgs &a, hipStream_t s) {
     if (a.n_hot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(unsigned(a.n_hot), unsigned(a.grids)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(unsigned(a.n_hot), unsigned((a.tile_cells + 255) / 256), unsigned(a.grids)),
+                       dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

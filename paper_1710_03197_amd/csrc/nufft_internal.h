@@ -15,9 +15,11 @@ constexpr int kMaxDim = 3;
 constexpr int kMaxJ = 16;
 constexpr int kMaxPasses = 16;     // radix passes per axis (K <= 8192)
 constexpr int kMaxNeighbors = 27;  // bins whose windows can reach one tile
-constexpr int kFftTileElems = 8192;  // complex elements of one FFT workgroup tile (64 KiB LDS)
-constexpr int kFftThreads = 512;
+constexpr int kFftTileElems = 8192;  // complex elements of the largest FFT workgroup tile (64 KiB LDS)
+constexpr int kMaxLinesPerWg = 64;   // lines (contiguous-axis passes) per FFT workgroup
 constexpr int kMaxPolyDeg = 23;
+constexpr int kInterpSamplesPerThread = 2;  // gather work item = 512 samples
+constexpr int kLdsBudget = 64 * 1024;      // bytes of LDS a gather or gridding tile may use
 
 // Radix schedule of one FFT axis (Stockham, product of r[] == K).
 struct RadixPlan {
@@ -118,6 +120,14 @@ struct SampleGeom {
 };
 
 // Interpolation V: y[g][perm[i]] = sum_taps w * G[g][..] for sorted sample i.
+// With items, one workgroup per (bin, chunk) stages the tile plus halo in LDS;
+// without (items == nullptr), one thread per sample reads the grid directly.
+struct InterpItem {
+    int bin;
+    int start;  // first sorted sample
+    int count;  // <= 256 * kInterpSamplesPerThread
+    int pad;
+};
 struct InterpArgs {
     SampleGeom geo;
     const float *om_sorted;  // [M][d]
@@ -127,6 +137,10 @@ struct InterpArgs {
     int64_t grid_elems;
     int grids;
     float2 *y;               // [grids][M]
+    const InterpItem *items;
+    int64_t n_items;
+    int T[kMaxDim];
+    int nt[kMaxDim];
 };
 hipError_t launch_interp(const InterpArgs &a, hipStream_t s);
 
@@ -148,12 +162,16 @@ struct GridArgs {
     SampleGeom geo;
     const float *om_sorted;
     const int *perm;
-    const int *bin_start;  // [nbins + 1]
+    const int *sub_start;  // [nbins * 2^d + 1] offsets of the (bin, crossing code) sub-bins
     int64_t M;
     int T[kMaxDim];
     int nt[kMaxDim];
     int R[kMaxDim];
     int tile_cells;
+    int seg_len;       // LS: cells of a tile row one lane accumulates (4, 8 or 16)
+    int segs;          // segments per tile row, ceil(T_last / LS)
+    int group_lanes;   // lanes per sample group: 64 * ceil(rows * segs / 64), rows = tile_cells / T_last
+    int stage_floats;  // LDS floats per group (staged batch, or the group's register tile at the end)
     int chunk;  // samples per work item
     const GridItem *items;
     int64_t n_items;
@@ -165,6 +183,48 @@ struct GridArgs {
     int64_t n_slots;
 };
 hipError_t launch_grid(const GridArgs &a, hipStream_t s);
+
+// Sorted-sample segments [lo, hi) whose windows reach tile tc: the whole own
+// bin, and from each lower neighbour bin (tc - e, e in {0,1}^d, e_a < R_a)
+// only the sub-bins whose crossing code contains e.  Shared by the plan (to
+// size work items) and the gridding kernel.  Returns the number of segments:
+// at most sum_e 2^(d - |e|) = 3^d - 2^d + 1, i.e. 2 in 1D, 6 in 2D, 20 in 3D.
+__host__ __device__ inline int tile_segments(int d, const int *tc, const int *nt, const int *R,
+                                             const int *sub_start, int *lo, int *hi) {
+    const int ncode = 1 << d;
+    int n = 0;
+    int e[kMaxDim] = {0, 0, 0};
+    while (true) {
+        int bin = 0, emask = 0;
+        for (int a = 0; a < d; ++a) {
+            int b = tc[a] - e[a];
+            if (b < 0) b += nt[a];
+            bin = bin * nt[a] + b;
+            emask |= e[a] << a;
+        }
+        const int base = bin * ncode;
+        if (emask == 0) {
+            lo[n] = sub_start[base];
+            hi[n] = sub_start[base + ncode];
+            ++n;
+        } else {
+            for (int c = 0; c < ncode; ++c) {
+                if ((c & emask) != emask) continue;
+                lo[n] = sub_start[base + c];
+                hi[n] = sub_start[base + c + 1];
+                ++n;
+            }
+        }
+        int a = d - 1;
+        while (a >= 0) {
+            if (++e[a] < R[a]) break;
+            e[a] = 0;
+            --a;
+        }
+        if (a < 0) break;
+    }
+    return n;
+}
 
 struct ReduceArgs {
     const HotTile *hot;

@@ -226,6 +226,90 @@ class Plan:
         return x
 
 
+class MultiPlan:
+    """P uneven problems (own N, K, M, trajectory, coils; shared d and J) run
+    together: nufft_multi_forward/adjoint capture all P transform sequences
+    into one HIP graph per set of buffers and replay it with one launch.
+
+    problems: list of dicts with keys om (float32 [M, d] device tensor), N,
+    K (default 2N), coils (complex64 [C, *N] device tensor or None)."""
+
+    def __init__(self, problems, J: int = 6):
+        self.device = problems[0]["om"].device
+        self.J = int(J)
+        self.problems = []
+        descs = (_lib.ProblemDesc * len(problems))()
+        keep = []
+        for i, pr in enumerate(problems):
+            om = pr["om"].contiguous()
+            N = tuple(int(n) for n in pr["N"])
+            K = tuple(2 * n for n in N) if pr.get("K") is None else tuple(int(k) for k in pr["K"])
+            d = len(N)
+            coils = pr.get("coils")
+            C = 0
+            if coils is not None:
+                coils = coils.contiguous()
+                C = int(coils.shape[0])
+                _need(coils, torch.complex64, (C,) + N, "coils", self.device)
+            _need(om, torch.float32, (om.shape[0], d), "om", self.device)
+            keep += [om, coils]
+            desc = descs[i]
+            desc.d, desc.J, desc.M, desc.C = d, self.J, int(om.shape[0]), C
+            for a in range(d):
+                desc.N[a] = N[a]
+                desc.K[a] = K[a]
+            desc.om = om.data_ptr() if om.shape[0] else None
+            desc.coils = coils.data_ptr() if coils is not None else None
+            self.problems.append(dict(N=N, K=K, M=int(om.shape[0]), C=C, d=d))
+        self._handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_multi_plan", len(problems), descs, _stream(self.device), ctypes.byref(self._handle))
+        del keep
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            _lib.call("nufft_multi_destroy", self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def yshape(self, p):
+        pr = self.problems[p]
+        return ((pr["C"],) if pr["C"] else ()) + (pr["M"],)
+
+    def _ptrs(self, ts, shapes, name):
+        arr = (ctypes.c_void_p * len(ts))()
+        for i, (t, shp) in enumerate(zip(ts, shapes)):
+            _need(t, torch.complex64, shp, f"{name}[{i}]", self.device)
+            arr[i] = t.data_ptr()
+        return arr
+
+    def forward(self, xs, ys=None):
+        """ys[p] = A_p xs[p] for every problem (coil mode: [C_p, M_p])."""
+        P = len(self.problems)
+        if ys is None:
+            ys = [torch.empty(self.yshape(p), dtype=torch.complex64, device=self.device) for p in range(P)]
+        xa = self._ptrs(xs, [pr["N"] for pr in self.problems], "x")
+        ya = self._ptrs(ys, [self.yshape(p) for p in range(P)], "y")
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_multi_forward", self._handle, xa, ya, _stream(self.device))
+        return ys
+
+    def adjoint(self, ys, xs=None):
+        P = len(self.problems)
+        if xs is None:
+            xs = [torch.empty(pr["N"], dtype=torch.complex64, device=self.device) for pr in self.problems]
+        ya = self._ptrs(ys, [self.yshape(p) for p in range(P)], "y")
+        xa = self._ptrs(xs, [pr["N"] for pr in self.problems], "x")
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_multi_adjoint", self._handle, ya, xa, _stream(self.device))
+        return xs
+
+
 def kernel_weights_host(J: int, sigma: float, f) -> tuple:
     """The per-tap weights (and derivatives) the GPU evaluates, computed on the
     host from the same polynomial fit: arrays [len(f), J]."""

@@ -3,7 +3,7 @@ same seeded float32 trajectories and complex64 inputs.
 
 Bar: relative L2 error <= 1e-5 (float32 arithmetic against float64), per
 stage and for the whole pair; batched and coil modes agree with looped single
-calls to 1e-6; the adjoint's run-to-run spread stays at float32 rounding.
+calls to 1e-6; the adjoint is bitwise reproducible run to run.
 """
 import numpy as np
 import pytest
@@ -113,18 +113,17 @@ def test_config3_full_size(orc, dev):
     p.close()
 
 
-def test_adjoint_run_to_run_spread_and_identity(orc, dev):
-    """LDS float atomics sum a tile's contributions in whatever order the waves
-    arrive, so repeated adjoints may differ in the last bits; the spread stays
-    at float32 rounding level."""
+def test_adjoint_is_deterministic_and_identity_holds(orc, dev):
+    """The gridding sums every tile in a fixed order (no atomics), so repeated
+    adjoints are bitwise identical; the float32 operator satisfies the adjoint
+    identity to float32 rounding."""
     c = data.config1()
     N, K, J, om = c["N"], c["K"], c["J"], c["om"]
     p = _plan(om, N, K, J, dev)
     y = _t(_rand_c((om.shape[0],), 3), dev)
     x1 = _np(p.adjoint(y))
-    spread = max(rel_l2(_np(p.adjoint(y)), x1) for _ in range(5))
-    print(f"adjoint run-to-run spread {spread:.2e}")
-    assert spread < 1e-6
+    for _ in range(3):
+        assert np.array_equal(_np(p.adjoint(y)).view(np.uint32), x1.view(np.uint32))
     xs = _rand_c(N, 4)
     Ax = _np(p.forward(_t(xs, dev))).astype(np.complex128)
     lhs = np.vdot(_np(y).astype(np.complex128), Ax)

@@ -310,3 +310,29 @@ def test_cg_against_dense_lstsq(orc):
     xc, _ = orc.cg(lambda p: (A.conj().T @ (A @ p.ravel())).reshape(N), (A.conj().T @ y).reshape(N), 300)
     xl = np.linalg.lstsq(A, y, rcond=None)[0].reshape(N)
     assert rel_l2(xc, xl) < 1e-8
+
+
+def test_cg_sensitivity_to_float32_level_operator_noise(orc):
+    """Ground for the GPU CG tolerance: a 30-step CG iterate moves by about
+    1e-3 of its norm when every operator application is perturbed at float32
+    level (1e-6 relative), while its error against the true image does not
+    change materially."""
+    N, K, J = (64, 64), (128, 128), 6
+    om = data.golden_radial_2d(64, 128)
+    x_true = data.ellipse_phantom(N, 10, np.random.default_rng(8)).astype(np.complex128)
+    y = orc.forward(x_true, om, N, K, J)
+    b = orc.adjoint(y, om, N, K, J)
+    rng = np.random.default_rng(9)
+
+    def normal(p):
+        return orc.adjoint(orc.forward(p, om, N, K, J), om, N, K, J)
+
+    def noisy(p):
+        q = normal(p)
+        return q * (1 + 1e-6 * (rng.standard_normal(q.shape) + 1j * rng.standard_normal(q.shape)))
+
+    x0, _ = orc.cg(normal, b, 30)
+    x1, _ = orc.cg(noisy, b, 30)
+    d = rel_l2(x1, x0)
+    assert 1e-5 < d < 1e-1
+    assert abs(rel_l2(x1, x_true) - rel_l2(x0, x_true)) < 0.02 * rel_l2(x0, x_true)
