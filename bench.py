@@ -96,6 +96,30 @@ def time_pairs(plan, x, y, xa, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def time_graph_pairs(plan, x, y, xa, steps, warmup):
+    """The same pair captured once into a HIP graph (torch.cuda.CUDAGraph) and
+    replayed: launch overhead removed, same kernels and work."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.forward(x, out=y)
+        plan.adjoint(y, out=xa)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.forward(x, out=y)
+        plan.adjoint(y, out=xa)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
 def kernel_times(plan, x, y, xa, steps):
     """Per-kernel launches and mean duration (ms) over `steps` pairs, from the
     library's HIP events on the launch stream."""
@@ -127,7 +151,21 @@ def roofline_entry(ktimes, alg, steps_hash):
                  "avg_launch_us": round(avg_ms * 1e3, 2)}
 
 
-def bench_2d(dev, steps, warmup, orc_mod):
+def make_plan(om_t, N, K, J, tune):
+    """The plan bench.py times: with tune=True, the autotuner's choice for this
+    workload (tuned now, every candidate parity-checked against the default
+    plan), else the built-in defaults."""
+    from paper_1710_03197_amd import Plan
+    if not tune:
+        return Plan(om_t, N, K, J), None
+    from paper_1710_03197_amd import autotune
+    res = autotune.tune(om_t, N, K, J, reps=10, save=False)
+    print(f"[bench] tuned {res['options']}: {res['ms_pair']:.4f} ms/pair (defaults {res['default_ms_pair']:.4f})",
+          flush=True)
+    return Plan(om_t, N, K, J, options=res["options"]), res
+
+
+def bench_2d(dev, steps, warmup, orc_mod, tune=True):
     import numpy as np
     import torch
     from paper_1710_03197_amd import Plan, data
@@ -135,7 +173,7 @@ def bench_2d(dev, steps, warmup, orc_mod):
     N, K, J, om = c["N"], c["K"], c["J"], c["om"]
     M = om.shape[0]
     print(f"[bench] 2D workload N={N} K={K} J={J} M={M}", flush=True)
-    plan = Plan(torch.from_numpy(om).to(dev), N, K, J)
+    plan, tuned = make_plan(torch.from_numpy(om).to(dev), N, K, J, tune)
     x = torch.from_numpy(c["x"]).to(dev)
     y = torch.empty(M, dtype=torch.complex64, device=dev)
     xa = torch.empty(N, dtype=torch.complex64, device=dev)
@@ -151,20 +189,22 @@ def bench_2d(dev, steps, warmup, orc_mod):
         raise SystemExit(f"parity gate failed: forward {err_f:.2e}, adjoint {err_a:.2e}")
     sec = time_pairs(plan, x, y, xa, steps, warmup)
     ktimes = kernel_times(plan, x, y, xa, steps)
+    sec_graph = time_graph_pairs(plan, x, y, xa, steps, warmup)
     alg = algorithmic_bytes(N, K, M, J)
     info = plan.info()
     plan.close()
-    return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f, err_a=err_a, N=N, K=K, M=M, J=J, info=info)
+    return dict(sec=sec, sec_graph=sec_graph, ktimes=ktimes, alg=alg, err_f=err_f, err_a=err_a, N=N, K=K, M=M,
+                J=J, info=info, tuned=tuned)
 
 
-def bench_3d(dev, steps, warmup, orc_mod):
+def bench_3d(dev, steps, warmup, orc_mod, tune=True):
     import torch
     from paper_1710_03197_amd import Plan, data
     c = data.config3()
     N, K, J, om = c["N"], c["K"], c["J"], c["om"]
     M = om.shape[0]
     print(f"[bench] 3D workload N={N} K={K} J={J} M={M}", flush=True)
-    plan = Plan(torch.from_numpy(om).to(dev), N, K, J)
+    plan, tuned = make_plan(torch.from_numpy(om).to(dev), N, K, J, tune)
     x = torch.from_numpy(c["x"]).to(dev)
     y = torch.empty(M, dtype=torch.complex64, device=dev)
     xa = torch.empty(N, dtype=torch.complex64, device=dev)
@@ -178,7 +218,7 @@ def bench_3d(dev, steps, warmup, orc_mod):
     ktimes = kernel_times(plan, x, y, xa, max(2, steps // 2))
     alg = algorithmic_bytes(N, K, M, J)
     plan.close()
-    return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f)
+    return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f, tuned=tuned)
 
 
 def bench_batched(dev, steps, warmup, orc_mod, n_problems=24):
@@ -270,6 +310,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="time the built-in defaults, skip the autotuner")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -285,17 +326,18 @@ def main():
     dev = torch.device("cuda:0")
     khash = kernels_hash()
 
-    r2 = bench_2d(dev, args.steps, args.warmup, orc_mod)
+    r2 = bench_2d(dev, args.steps, args.warmup, orc_mod, tune=not args.no_tune)
     dom, roof = roofline_entry(r2["ktimes"], r2["alg"], khash)
     extra = {
         "rel_err_forward": r2["err_f"], "rel_err_adjoint": r2["err_a"],
         "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r2["ktimes"].items()},
+        "graph_replay_pairs_per_s": round(1.0 / r2["sec_graph"], 2),
         "pair_bytes_model": int(sum(r2["alg"].values())),
         "pair_model_frac": round(sum(r2["alg"].values()) / r2["sec"] / 1e9 / HBM_PEAK_GBS, 4),
-        "plan": r2["info"], "kernels_sha": khash,
+        "plan": r2["info"], "kernels_sha": khash, "tuning": r2["tuned"],
     }
     if not args.no_3d:
-        r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod)
+        r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod, tune=not args.no_tune)
         _, roof3 = roofline_entry(r3["ktimes"], r3["alg"], khash)
         extra["3d_128"] = {
             "pairs_per_s": round(1.0 / r3["sec"], 2), "ms_per_pair": round(r3["sec"] * 1e3, 4),
@@ -304,6 +346,7 @@ def main():
             "pair_model_frac": round(sum(r3["alg"].values()) / r3["sec"] / 1e9 / HBM_PEAK_GBS, 4),
             "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r3["ktimes"].items()},
             "roofline": roof3,
+            "tuning": r3["tuned"],
         }
     if not args.no_batched:
         extra["batched_vs_looped"] = bench_batched(dev, max(3, args.steps // 40), 2, orc_mod)

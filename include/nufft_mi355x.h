@@ -67,7 +67,7 @@ typedef struct nufft_plan_s *nufft_plan_t;
 /* Create a plan for the d-dimensional pair (Section 2.1, Eq. A = VFS).
  *   d      : 1, 2 or 3.
  *   N[d]   : image size per axis, even, >= 2.
- *   K[d]   : oversampled grid size per axis, even, K_a >= N_a, K_a <= 8192,
+ *   K[d]   : oversampled grid size per axis, even, K_a >= N_a, K_a <= 4096,
  *            and K_a has no prime factor above 5 (mixed-radix 2/3/4/5/8 FFT).
  *   J      : taps per axis, 2 <= J <= 16 and J <= K_a.
  *   M      : number of samples, 0 <= M < 2^31.
@@ -78,6 +78,25 @@ typedef struct nufft_plan_s *nufft_plan_t;
  * Errors: INVALID_ARG, NO_DEVICE, OOM, HIP, NONFINITE (no plan is returned). */
 int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
                const float *om_dev, void *stream, nufft_plan_t *out);
+
+/* Tuning knobs of a plan; 0 in any field keeps the built-in default.  Any
+ * choice gives the same operator (to float32 rounding); only speed changes.
+ *   tile[a]       grid tile edge on axis a for binning, gathering and
+ *                 gridding (rounded to a divisor of K_a that is >= J - 1)
+ *   grid_chunk    samples per gridding work item (>= 64)
+ *   fft_groups    workgroups the FFT passes aim to launch (sets lines or
+ *                 columns per workgroup)
+ * Used by the autotuner (paper_1710_03197_amd/autotune.py). */
+typedef struct {
+    int tile[3];
+    int grid_chunk;
+    int fft_groups;
+    int reserved[3];
+} nufft_options_t;
+
+/* nufft_plan with tuning options (opt may be NULL = defaults). */
+int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, const float *om_dev,
+                  const nufft_options_t *opt, void *stream, nufft_plan_t *out);
 
 /* Replace the trajectory (same M) and re-bin it; synchronises `stream`.
  * On NONFINITE the plan keeps its previous trajectory. */

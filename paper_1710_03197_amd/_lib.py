@@ -36,6 +36,12 @@ class NufftError(RuntimeError):
 _lib = None
 
 
+class PlanOptions(ctypes.Structure):
+    """nufft_options_t of include/nufft_mi355x.h (0 = default)."""
+    _fields_ = [("tile", ctypes.c_int * 3), ("grid_chunk", ctypes.c_int), ("fft_groups", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
+
+
 class ProblemDesc(ctypes.Structure):
     """nufft_problem_t of include/nufft_mi355x.h."""
     _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int64 * 3), ("K", ctypes.c_int64 * 3),
@@ -50,6 +56,8 @@ _ip = ctypes.POINTER(ctypes.c_int)
 
 _SIGS = {
     "nufft_plan": [ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int64, _vp, _vp, ctypes.POINTER(_vp)],
+    "nufft_plan_ex": [ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int64, _vp, ctypes.POINTER(PlanOptions),
+                      _vp, ctypes.POINTER(_vp)],
     "nufft_set_points": [_vp, _vp, _vp],
     "nufft_set_coils": [_vp, ctypes.c_int, _vp],
     "nufft_reserve": [_vp, ctypes.c_int],

@@ -1,0 +1,167 @@
+"""Autotuner for the NUFFT plan's launch parameters.
+
+Chooses, per workload, the grid tile shape used for binning, gathering and
+gridding, the number of samples per gridding work item, and how many
+workgroups the FFT passes aim for (lines or columns per workgroup).  These
+change only speed: every candidate's forward and adjoint outputs must agree
+with the default plan's to 1e-5 (relative L2) before it may win, and the
+default plan is the one the parity tests hold to the FP64 oracle.
+
+Results are cached in JSON, keyed by GPU architecture, d, N, K, J and M
+rounded to a power of two, at $NUFFT_TUNE_CACHE or
+~/.cache/nufft_mi355x/tune.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from .plan import Plan
+
+TOL = 1e-5
+
+TILE_CANDIDATES = {
+    1: [(32,), (64,), (16,)],
+    2: [(32, 16), (64, 16), (16, 16), (32, 32), (16, 32), (64, 8)],
+    3: [(8, 8, 16), (8, 8, 8), (4, 8, 16), (8, 4, 16), (4, 4, 16), (16, 8, 8)],
+}
+CHUNK_CANDIDATES = [256, 512, 1024, 2048]
+FFT_GROUP_CANDIDATES = [256, 512, 1024, 2048, 4096]
+
+
+def cache_path(path: str | None = None) -> str:
+    if path:
+        return path
+    env = os.environ.get("NUFFT_TUNE_CACHE")
+    if env:
+        return env
+    return os.path.join(os.path.expanduser("~"), ".cache", "nufft_mi355x", "tune.json")
+
+
+def workload_key(N, K, J, M, device=None) -> str:
+    arch = torch.cuda.get_device_properties(device or 0).gcnArchName.split(":")[0]
+    mb = 1 << max(0, int(round(math.log2(max(M, 1)))))
+    return f"{arch}|d{len(N)}|N{'x'.join(map(str, N))}|K{'x'.join(map(str, K))}|J{J}|M~{mb}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _rel(a, b):
+    return float(torch.linalg.vector_norm((a - b).flatten()) / torch.linalg.vector_norm(b.flatten()))
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | None = None,
+         save: bool = True, verbose: bool = False) -> dict:
+    """Tune the plan options for trajectory `om` (float32 [M, d] on the GPU).
+    Returns {"options": ..., "ms_pair": ..., "default_ms_pair": ..., "tried": n}."""
+    N = tuple(int(n) for n in N)
+    K = tuple(2 * n for n in N) if K is None else tuple(int(k) for k in K)
+    d, M = len(N), int(om.shape[0])
+    dev = om.device
+    g = torch.Generator(device="cpu").manual_seed(1234)
+    x = torch.complex(torch.randn(N, generator=g), torch.randn(N, generator=g)).to(dev)
+    yin = torch.complex(torch.randn(M, generator=g), torch.randn(M, generator=g)).to(dev)
+
+    ref = Plan(om, N, K, J)
+    y_ref, x_ref = ref.forward(x), ref.adjoint(yin)
+
+    def pair_time(p):
+        y = torch.empty(M, dtype=torch.complex64, device=dev)
+        xa = torch.empty(N, dtype=torch.complex64, device=dev)
+        return _time(lambda: (p.forward(x, out=y), p.adjoint(yin, out=xa)), reps)
+
+    def sample_stage_time(p):
+        G = torch.empty(K, dtype=torch.complex64, device=dev)
+        return _time(lambda: (p.stage_v(G), p.stage_vh(yin)), reps)
+
+    def valid(p):
+        return _rel(p.forward(x), y_ref) <= TOL and _rel(p.adjoint(yin), x_ref) <= TOL
+
+    default_ms = pair_time(ref)
+    ref.close()
+    tried = 0
+    # 1) tile shape and gridding chunk, timed on the two sample stages
+    best, best_t = {}, float("inf")
+    for tile in TILE_CANDIDATES[d]:
+        for chunk in CHUNK_CANDIDATES:
+            opts = dict(tile=tile, grid_chunk=chunk)
+            try:
+                p = Plan(om, N, K, J, options=opts)
+            except RuntimeError:
+                continue
+            tried += 1
+            if not valid(p):
+                p.close()
+                continue
+            t = sample_stage_time(p)
+            p.close()
+            if verbose:
+                print(f"[tune] {opts}: sample stages {t:.4f} ms", flush=True)
+            if t < best_t:
+                best, best_t = opts, t
+    # 2) FFT workgroup target with that tiling, timed on the whole pair
+    best_pair, best_pt = dict(best), float("inf")
+    for groups in FFT_GROUP_CANDIDATES:
+        opts = dict(best, fft_groups=groups)
+        p = Plan(om, N, K, J, options=opts)
+        tried += 1
+        if not valid(p):
+            p.close()
+            continue
+        t = pair_time(p)
+        p.close()
+        if verbose:
+            print(f"[tune] {opts}: pair {t:.4f} ms", flush=True)
+        if t < best_pt:
+            best_pair, best_pt = opts, t
+    result = {"options": {k: list(v) if isinstance(v, tuple) else v for k, v in best_pair.items()},
+              "ms_pair": best_pt, "default_ms_pair": default_ms, "tried": tried}
+    if save:
+        cp = cache_path(path)
+        os.makedirs(os.path.dirname(cp), exist_ok=True)
+        db = _load(cp)
+        db[workload_key(N, K, J, M, dev)] = result
+        tmp = cp + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, cp)
+    return result
+
+
+def cached_options(N, K, J, M, path: str | None = None, device=None) -> dict | None:
+    N = tuple(int(n) for n in N)
+    K = tuple(2 * n for n in N) if K is None else tuple(int(k) for k in K)
+    entry = _load(cache_path(path)).get(workload_key(N, K, J, M, device))
+    return None if entry is None else entry["options"]
+
+
+def tuned_plan(om: torch.Tensor, N, K=None, J: int = 6, coils=None, path: str | None = None,
+               tune_if_missing: bool = False) -> Plan:
+    """A Plan with the cached tuned options for this workload (tuning first if
+    asked and nothing is cached; defaults otherwise)."""
+    opts = cached_options(N, K, J, int(om.shape[0]), path, om.device)
+    if opts is None and tune_if_missing:
+        opts = tune(om, N, K, J, path=path)["options"]
+    return Plan(om, N, K, J, coils=coils, options=opts)

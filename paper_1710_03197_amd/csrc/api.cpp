@@ -97,6 +97,7 @@ struct nufft_plan_s {
     int tile_cells = 1;
     int64_t nbins = 1;
     int chunk = 2048;
+    int fft_groups = 1024;
     int64_t img_elems = 1, grid_elems = 1, tmp_elems = 1;
 
     // device constants
@@ -336,6 +337,35 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         const int b0 = start[size_t(t) << d], b1 = start[size_t(t + 1) << d];
         for (int f = b0; f < b1; f += ichunk) iitems.push_back(InterpItem{int(t), f, std::min(ichunk, b1 - f), 0});
     }
+    // Longest items first: workgroups are dealt to the XCDs round-robin in
+    // launch order, so the crowded tiles (all at the k-space centre, i.e. at
+    // the two ends of the tile order) spread over the whole chip and the
+    // light tiles fill in behind them.
+    {
+        std::vector<int64_t> cnt(items.size());
+        std::vector<int> ord(items.size());
+        for (size_t q = 0; q < items.size(); ++q) {
+            const GridItem &gi = items[q];
+            int tc[kMaxDim];
+            int64_t rem = gi.tile;
+            for (int a = d - 1; a >= 0; --a) {
+                tc[a] = int(rem % p->nt[a]);
+                rem /= p->nt[a];
+            }
+            int lo[kMaxNeighbors], hi[kMaxNeighbors];
+            const int nseg = tile_segments(d, tc, p->nt, p->R, start.data(), lo, hi);
+            int64_t S = 0;
+            for (int k = 0; k < nseg; ++k) S += hi[k] - lo[k];
+            cnt[q] = std::min<int64_t>(p->chunk, S - int64_t(gi.chunk) * p->chunk);
+            ord[q] = int(q);
+        }
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cnt[x] > cnt[y]; });
+        std::vector<GridItem> sorted(items.size());
+        for (size_t q = 0; q < ord.size(); ++q) sorted[q] = items[ord[q]];
+        items.swap(sorted);
+        std::stable_sort(iitems.begin(), iitems.end(),
+                         [](const InterpItem &x, const InterpItem &y) { return x.count > y.count; });
+    }
     dfree(p->sub_start);
     dfree(p->items);
     dfree(p->iitems);
@@ -399,6 +429,7 @@ int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) 
             a.rows = 1;
             for (int b = 0; b < d - 1; ++b) a.rows *= p->N[b];
             a.d = d;
+            a.target_groups = p->fft_groups;
             for (int b = 0; b < d; ++b) {
                 a.Nax[b] = int(p->N[b]);
                 a.scale[b] = p->scale[b];
@@ -419,6 +450,7 @@ int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) 
             for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
             a.grids = grids;
             a.inverse = false;
+            a.target_groups = p->fft_groups;
             HIP_TRY(timed(p, kStridedFwd, s, [&] { return launch_strided_pass(a, s); }), "forward strided FFT pass");
         }
         cur = dst;
@@ -447,6 +479,7 @@ int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s) 
             a.rows = 1;
             for (int b = 0; b < d - 1; ++b) a.rows *= p->N[b];
             a.d = d;
+            a.target_groups = p->fft_groups;
             for (int b = 0; b < d; ++b) {
                 a.Nax[b] = int(p->N[b]);
                 a.scale[b] = p->scale[b];
@@ -468,6 +501,7 @@ int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s) 
             for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
             a.grids = grids;
             a.inverse = true;
+            a.target_groups = p->fft_groups;
             HIP_TRY(timed(p, kStridedInv, s, [&] { return launch_strided_pass(a, s); }), "adjoint strided FFT pass");
             cur = dst;
         }
@@ -788,6 +822,11 @@ int nufft_kernel_weights_host(int J, double sigma, int64_t n, const double *f, d
 
 int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, const float *om_dev, void *stream,
                nufft_plan_t *out) {
+    return nufft_plan_ex(d, N, K, J, M, om_dev, nullptr, stream, out);
+}
+
+int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, const float *om_dev,
+                  const nufft_options_t *opt, void *stream, nufft_plan_t *out) {
     if (!out) return fail(NUFFT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (d < 1 || d > kMaxDim) return fail(NUFFT_ERR_INVALID_ARG, "d=%d must be 1, 2 or 3", d);
@@ -799,7 +838,7 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, cons
     for (int a = 0; a < d; ++a) {
         if (N[a] < 2 || N[a] % 2) return fail(NUFFT_ERR_INVALID_ARG, "N[%d]=%lld must be even and >= 2", a, (long long)N[a]);
         if (K[a] < N[a] || K[a] % 2) return fail(NUFFT_ERR_INVALID_ARG, "K[%d]=%lld must be even and >= N", a, (long long)K[a]);
-        if (K[a] > 8192) return fail(NUFFT_ERR_UNSUPPORTED, "K[%d]=%lld above 8192", a, (long long)K[a]);
+        if (K[a] > 4096) return fail(NUFFT_ERR_UNSUPPORTED, "K[%d]=%lld above 4096", a, (long long)K[a]);
         if (!smooth235(K[a])) return fail(NUFFT_ERR_UNSUPPORTED, "K[%d]=%lld has a prime factor above 5", a, (long long)K[a]);
         if (J > K[a]) return fail(NUFFT_ERR_INVALID_ARG, "J=%d exceeds K[%d]", J, a);
         img *= N[a];
@@ -843,7 +882,8 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, cons
         if (!kb_fit(J, kb_beta(J, double(K[a]) / double(N[a])), &p->ker[a]))
             return bail(fail(NUFFT_ERR_UNSUPPORTED, "kernel polynomial fit did not converge"));
         if (!radix_plan(int(K[a]), &p->rp[a])) return bail(fail(NUFFT_ERR_UNSUPPORTED, "no radix plan for K"));
-        p->T[a] = choose_tile(K[a], targets[d - 1][a], std::max(1, need));
+        const int target = (opt && opt->tile[a] > 0) ? opt->tile[a] : targets[d - 1][a];
+        p->T[a] = choose_tile(K[a], target, std::max(1, need));
         p->nt[a] = int(K[a] / p->T[a]);
         p->R[a] = p->nt[a] > 1 ? 2 : 1;
         p->tile_cells *= p->T[a];
@@ -892,11 +932,13 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M, cons
         p->staged_interp = region <= kLdsBudget;
     }
     if ((p->nbins << d) >= (int64_t(1) << 30)) return bail(fail(NUFFT_ERR_UNSUPPORTED, "too many bins"));
-    p->chunk = d == 1 ? 2048 : 1024;
-    if (const char *env = std::getenv("NUFFT_GRID_CHUNK")) {  // tuning override
-        const int c = std::atoi(env);
-        if (c >= 64) p->chunk = c;
+    p->chunk = d == 3 ? 1024 : 512;
+    if (opt && opt->grid_chunk > 0) {
+        if (opt->grid_chunk < 64) return bail(fail(NUFFT_ERR_INVALID_ARG, "grid_chunk below 64"));
+        p->chunk = opt->grid_chunk;
     }
+    if (opt && opt->fft_groups < 0) return bail(fail(NUFFT_ERR_INVALID_ARG, "fft_groups negative"));
+    p->fft_groups = (opt && opt->fft_groups > 0) ? opt->fft_groups : 1024;
     // intermediate sizes of the FFT passes that land in the tmp buffer
     p->tmp_elems = 1;
     for (int pass = 0; pass < d - 1; ++pass) {

@@ -121,7 +121,7 @@ __device__ __forceinline__ void dft<8>(float2 *v) {
 // holds at most THREADS * kEPT complex elements; a thread handles up to
 // ceil(kEPT / R) butterflies of radix R per pass.  Twiddles e^{-2 pi i e / K}
 // are staged in LDS (tw) once per workgroup.
-constexpr int kEPT = 16;  // complex elements per thread
+constexpr int kEPT = 8;  // complex elements per thread
 
 template <int THREADS, int R, bool INV, bool STRIDED>
 __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS, int ES, int Ns,
@@ -394,15 +394,10 @@ __device__ __forceinline__ void window_weights(const float *__restrict__ coef, i
 }
 
 // ------------------------------------------------------------ work distribution
-// Workgroup b of n runs item xcd_item(b, n): the hardware deals consecutive
-// workgroups round-robin over the 8 XCDs, so this hands each XCD a contiguous
-// run of items (neighbouring tiles), whose shared halos and neighbour samples
-// then stay in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
-    const int64_t x = b & 7, idx = b >> 3;
-    const int64_t q = n >> 3, r = n & 7;
-    return x * q + min(x, r) + idx;
-}
+// Work items (gather chunks, gridding tile chunks) are ordered by decreasing
+// size on the host; workgroup b runs item b, and the hardware deals
+// consecutive workgroups round-robin over the 8 XCDs, so the heavy items
+// spread over the whole chip.
 
 // ------------------------------------------------------------ V (gather)
 // One workgroup per (bin, chunk): the tile and its J-1 halo of the grid are
@@ -411,7 +406,7 @@ __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
 template <int J, int DIM>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
     extern __shared__ float2 reg[];
-    const InterpItem it = a.items[xcd_item(blockIdx.x, gridDim.x)];
+    const InterpItem it = a.items[blockIdx.x];
     int tc[DIM], base[DIM], E[DIM];
     {
         int t = it.bin;
@@ -572,6 +567,19 @@ __global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
 // order, so the result does not depend on scheduling.
 constexpr int kGridThreads = 256;
 
+// Synchronise a lane group's LDS traffic: a single wavefront only needs its
+// own LDS operations ordered (lockstep execution), larger groups need the
+// workgroup barrier.
+__device__ __forceinline__ void group_sync(int gsize) {
+    if (gsize == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <int DIM, int LS>
 __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     extern __shared__ float4 stage_mem[];  // float4: 16-byte aligned rows for the vector reads
@@ -580,7 +588,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     __shared__ int seg_hi[kMaxNeighbors];
     __shared__ int seg_pre[kMaxNeighbors + 1];
     __shared__ int nseg_s;
-    const GridItem it = a.items[xcd_item(blockIdx.x, gridDim.x)];
+    const GridItem it = a.items[blockIdx.x];
     const int g = blockIdx.y;
     const int J = a.geo.J;
     const int L = a.T[DIM - 1];           // cells per tile row
@@ -646,6 +654,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
 #pragma unroll
     for (int c = 0; c < LS; ++c) acc[c] = make_float2(0.f, 0.f);
 
+    // A group of one wavefront stages and consumes its own batches, so it
+    // synchronises only with itself and runs ahead of the other groups.
     const int per_iter = B * ngroups;
     for (int b0 = 0; b0 < n; b0 += per_iter) {
         // ---- stage one batch per group: lane `lane` stages sample b0 + grp*B + lane
@@ -655,8 +665,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
             int sg = 0;
             while (sg + 1 < nseg && seg_pre[sg + 1] <= f) ++sg;
             const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
-            float *wr = wrow + lane * Lp;
-            for (int c = 0; c < Lp; ++c) wr[c] = 0.f;
+            float wl_row[kMaxJ];  // last-axis weights, spread on the row below
+            int o_last = 0;
 #pragma unroll
             for (int ax = 0; ax < DIM; ++ax) {
                 const double u = __dmul_rn(double(a.om_sorted[i * DIM + ax]), a.geo.C[ax]);
@@ -676,19 +686,38 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                     for (int q = deg - 1; q >= 0; --q) v = fmaf(v, z, cj[q]);
                     if (ax < DIM - 1) {
                         sw[(ax * J + j) * BP + lane] = v;
-                    } else {
-                        int c = o + j;
-                        if (a.nt[ax] == 1 && c >= K) c -= K;
-                        if (c >= 0 && c < L) wr[c] = v;
+                    } else if (j < kMaxJ) {
+                        wl_row[j] = v;
                     }
                 }
                 if (ax < DIM - 1) so[ax * BP + lane] = o;
+                else o_last = o;
+            }
+            // the tile row of last-axis weights: cell c gets w[c - o] (wrapping
+            // when the axis is one tile), built in registers and stored with
+            // 16-byte writes
+            const int Kl = a.geo.K[DIM - 1];
+            const bool wrapl = a.nt[DIM - 1] == 1;
+            float4 *wr4 = reinterpret_cast<float4 *>(wrow + lane * Lp);
+            for (int c4 = 0; c4 < Lp; c4 += 4) {
+                float r[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    int j = c4 + u - o_last;
+                    if (wrapl && j < 0) j += Kl;
+                    float v = 0.f;
+#pragma unroll
+                    for (int jj = 0; jj < kMaxJ; ++jj)
+                        if (jj < J && j == jj) v = wl_row[jj];
+                    r[u] = (c4 + u < L) ? v : 0.f;
+                }
+                wr4[c4 >> 2] = make_float4(r[0], r[1], r[2], r[3]);
             }
             const float2 v = y[a.perm[i]];
             sv[lane] = v.x;
             sv[BP + lane] = v.y;
         }
-        __syncthreads();
+        group_sync(gsize);
         // ---- every lane of the group walks the group's batch
         const int nb = min(B, n - (b0 + grp * B));
 #pragma unroll 2
@@ -717,12 +746,13 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                 acc[4 * q + 3].y = fmaf(w.w, vi, acc[4 * q + 3].y);
             }
         }
-        __syncthreads();
+        group_sync(gsize);
     }
     // ---- combine the groups' register tiles (group order), write the tile
     float2 *red = reinterpret_cast<float2 *>(stage);  // [ngroups][lead][Lp], reuses the staging LDS
     const bool seg_ok = row_ok;
     if (ngroups > 1) {
+        __syncthreads();  // every group is done with its staging area
         if (seg_ok) {
 #pragma unroll
             for (int c = 0; c < LS; ++c) red[(grp * lead + row) * Lp + cseg + c] = acc[c];
@@ -984,10 +1014,9 @@ struct GradLaunch {
 };
 
 // FFT tile sizes: a tile holds up to THREADS * kEPT elements.  The host takes
-// the largest tile that still leaves about kFftTargetGroups workgroups (small
+// the largest tile that still leaves about target_groups workgroups (small
 // transforms spread over the whole chip), then the smallest block that holds
 // it.
-constexpr int64_t kFftTargetGroups = 1024;
 
 template <template <int> class L, class A>
 hipError_t fft_dispatch(int threads, const A &a, hipStream_t s, int p0, int64_t p1, size_t lds, unsigned blocks) {
@@ -1036,7 +1065,7 @@ hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s) {
     const int64_t total = int64_t(a.B) * a.C * a.rows;
     if (total == 0) return hipSuccess;
     const int cap = kFftTileElems / a.K;  // lines that fit the largest tile
-    int lpw = int(std::min<int64_t>(std::max<int64_t>(1, total / kFftTargetGroups), std::min(cap, kMaxLinesPerWg)));
+    int lpw = int(std::min<int64_t>(std::max<int64_t>(1, total / a.target_groups), std::min(cap, kMaxLinesPerWg)));
     lpw = std::max(1, lpw);
     const int threads = threads_for(lpw * a.K);
     const int64_t blocks = (total + lpw - 1) / lpw;
@@ -1049,7 +1078,7 @@ hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s) {
     if (columns == 0) return hipSuccess;
     const int cap = std::max(1, kFftTileElems / a.K);
     // columns per tile: at least 4 adjacent (32-byte rows), fewer only for narrow arrays
-    int64_t W = std::max<int64_t>(4, columns / kFftTargetGroups);
+    int64_t W = std::max<int64_t>(4, columns / a.target_groups);
     W = std::min<int64_t>(W, cap);
     W = std::min<int64_t>(W, a.inner);
     W = std::max<int64_t>(W, 1);
@@ -1078,7 +1107,7 @@ hipError_t launch_last_pass(const LastPassArgs &a, hipStream_t s) {
     if (a.C * a.K <= kFftTileElems) {
         coils_per_round = a.C;
         const int cap = std::min(kFftTileElems / (a.C * a.K), kMaxLinesPerWg);
-        rows_per_wg = int(std::min<int64_t>(std::max<int64_t>(1, total_rows / kFftTargetGroups), cap));
+        rows_per_wg = int(std::min<int64_t>(std::max<int64_t>(1, total_rows / a.target_groups), cap));
     } else {
         rows_per_wg = 1;
         coils_per_round = std::max(1, kFftTileElems / a.K);

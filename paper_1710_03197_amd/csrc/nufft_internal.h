@@ -13,9 +13,9 @@ namespace nufft {
 
 constexpr int kMaxDim = 3;
 constexpr int kMaxJ = 16;
-constexpr int kMaxPasses = 16;     // radix passes per axis (K <= 8192)
+constexpr int kMaxPasses = 16;     // radix passes per axis (K <= 4096)
 constexpr int kMaxNeighbors = 27;  // bins whose windows can reach one tile
-constexpr int kFftTileElems = 8192;  // complex elements of the largest FFT workgroup tile (64 KiB LDS)
+constexpr int kFftTileElems = 4096;  // complex elements of the largest FFT workgroup tile (512 threads x 8)
 constexpr int kMaxLinesPerWg = 64;   // lines (contiguous-axis passes) per FFT workgroup
 constexpr int kMaxPolyDeg = 23;
 constexpr int kInterpSamplesPerThread = 2;  // gather work item = 512 samples
@@ -73,6 +73,7 @@ struct FirstPassArgs {
     int d;
     int Nax[kMaxDim];
     const float *scale[kMaxDim];
+    int target_groups;  // workgroups the launch aims for
 };
 hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s);
 
@@ -87,6 +88,7 @@ struct StridedPassArgs {
     int64_t outer, inner;
     int64_t grids;
     bool inverse;
+    int target_groups;
 };
 hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s);
 
@@ -104,6 +106,7 @@ struct LastPassArgs {
     int d;
     int Nax[kMaxDim];
     const float *scale[kMaxDim];
+    int target_groups;
 };
 hipError_t launch_last_pass(const LastPassArgs &a, hipStream_t s);
 

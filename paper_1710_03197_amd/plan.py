@@ -41,7 +41,8 @@ class Plan:
     trajectory `om` (float32 [M, d] on a HIP device).  Optional `coils`
     (complex64 [C, *N]) switch on coil mode (paper Section 2.2)."""
 
-    def __init__(self, om: torch.Tensor, N, K=None, J: int = 6, coils: torch.Tensor | None = None):
+    def __init__(self, om: torch.Tensor, N, K=None, J: int = 6, coils: torch.Tensor | None = None,
+                 options: dict | None = None):
         N = tuple(int(n) for n in N)
         d = len(N)
         K = tuple(2 * n for n in N) if K is None else tuple(int(k) for k in K)
@@ -57,9 +58,15 @@ class Plan:
         self._handle = ctypes.c_void_p()
         n_arr = (ctypes.c_int64 * d)(*N)
         k_arr = (ctypes.c_int64 * d)(*K)
+        self.options = dict(options or {})
+        opt = _lib.PlanOptions()
+        for a, t in enumerate(self.options.get("tile", ())[:3]):
+            opt.tile[a] = int(t)
+        opt.grid_chunk = int(self.options.get("grid_chunk", 0))
+        opt.fft_groups = int(self.options.get("fft_groups", 0))
         with torch.cuda.device(self.device):
-            _lib.call("nufft_plan", d, n_arr, k_arr, self.J, self.M,
-                      _ptr(om) if self.M else ctypes.c_void_p(), _stream(self.device),
+            _lib.call("nufft_plan_ex", d, n_arr, k_arr, self.J, self.M,
+                      _ptr(om) if self.M else ctypes.c_void_p(), ctypes.byref(opt), _stream(self.device),
                       ctypes.byref(self._handle))
         if coils is not None:
             self.set_coils(coils)

@@ -44,7 +44,7 @@ def test_status_strings():
     (1, (8,), (16,), 6, -5, -1),           # negative M
     (1, (8,), (16,), 6, 10, -1),           # om NULL with M > 0
     (1, (8,), (14,), 6, 0, -7),            # prime factor 7
-    (1, (8,), (16384,), 6, 0, -7),         # K above 8192
+    (1, (8,), (8192,), 6, 0, -7),          # K above 4096
 ])
 def test_plan_argument_validation(d, N, K, J, M, code):
     st, h = _plan(d, N, K, J, M)
