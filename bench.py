@@ -32,11 +32,17 @@ METRIC = "NUFFT fwd+adj pairs/s, 2D 256² & 3D 128³ at rel err≤1e-5; batched 
 TOL = 1e-5
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
-# this benchmark (KiB per dispatch), with the scale factor measured on a plain
-# copy kernel of known size.  Keyed by the sha256 of kernels.hip when the
-# counters were taken: after any change to the kernels the entry no longer
-# applies and traffic is reported as null.
-MEASURED_TRAFFIC: dict = {}
+# this benchmark (KiB per dispatch), each scaled by what the counter reports for
+# a 256 MiB device-to-device copy (reads: x2.000, writes: x1.000); see
+# profiles/traffic_2d_256_radial.md.  An entry applies only while kernels.hip
+# has the recorded sha256 prefix and the plan uses the recorded options;
+# otherwise traffic is reported as null.
+MEASURED_TRAFFIC: dict = {
+    "k_grid": {"kernels_sha": "49a38d78bdde92ab", "workload": "2d_256_golden_radial",
+               "options": {"fft_groups": 256, "grid_chunk": 256, "tile": [16, 16]},
+               "fetch_kib": 3696.0, "write_kib": 2868.0, "read_scale": 2.0, "write_scale": 1.0,
+               "bytes_per_launch": 10505053},
+}
 
 
 def kernels_hash() -> str:
@@ -135,7 +141,7 @@ def kernel_times(plan, x, y, xa, steps):
     return {k: (n / steps, ms / n) for k, (n, ms) in rep.items()}
 
 
-def roofline_entry(ktimes, alg, steps_hash):
+def roofline_entry(ktimes, alg, steps_hash, workload=None, options=None):
     """Roofline of the kernel with the largest share of the pair's time."""
     dom = max(ktimes, key=lambda k: ktimes[k][0] * ktimes[k][1])
     launches_per_pair, avg_ms = ktimes[dom]
@@ -143,7 +149,8 @@ def roofline_entry(ktimes, alg, steps_hash):
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     m = MEASURED_TRAFFIC.get(dom)
-    if m and m.get("kernels_sha") == steps_hash:
+    if (m and m.get("kernels_sha") == steps_hash and m.get("workload") == workload
+            and m.get("options") == options):
         traffic = m["bytes_per_launch"]
     return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -152,20 +159,24 @@ def roofline_entry(ktimes, alg, steps_hash):
 
 
 def make_plan(om_t, N, K, J, tune):
-    """The plan bench.py times: with tune=True, the autotuner's choice for this
-    workload (tuned now, every candidate parity-checked against the default
-    plan), else the built-in defaults."""
-    from paper_1710_03197_amd import Plan
-    if not tune:
+    """The plan bench.py times.  tune="cache": the options the autotuner stored
+    for this workload in paper_1710_03197_amd/tuning_gfx950.json (defaults if
+    absent); "now": tune here (every candidate parity-checked against the
+    default plan); "off": built-in defaults."""
+    from paper_1710_03197_amd import Plan, autotune
+    if tune == "off":
         return Plan(om_t, N, K, J), None
-    from paper_1710_03197_amd import autotune
-    res = autotune.tune(om_t, N, K, J, reps=10, save=False)
-    print(f"[bench] tuned {res['options']}: {res['ms_pair']:.4f} ms/pair (defaults {res['default_ms_pair']:.4f})",
-          flush=True)
-    return Plan(om_t, N, K, J, options=res["options"]), res
+    if tune == "now":
+        res = autotune.tune(om_t, N, K, J, reps=10, save=False)
+        print(f"[bench] tuned {res['options']}: {res['ms_pair']:.4f} ms/pair (defaults {res['default_ms_pair']:.4f})",
+              flush=True)
+        return Plan(om_t, N, K, J, options=res["options"]), dict(res, source="tuned in this run")
+    opts = autotune.cached_options(N, K, J, int(om_t.shape[0]), autotune.SHIPPED_CACHE, om_t.device)
+    print(f"[bench] options from the tuning cache: {opts}", flush=True)
+    return Plan(om_t, N, K, J, options=opts), {"options": opts, "source": "paper_1710_03197_amd/tuning_gfx950.json"}
 
 
-def bench_2d(dev, steps, warmup, orc_mod, tune=True):
+def bench_2d(dev, steps, warmup, orc_mod, tune="cache", no_graph=False):
     import numpy as np
     import torch
     from paper_1710_03197_amd import Plan, data
@@ -189,7 +200,7 @@ def bench_2d(dev, steps, warmup, orc_mod, tune=True):
         raise SystemExit(f"parity gate failed: forward {err_f:.2e}, adjoint {err_a:.2e}")
     sec = time_pairs(plan, x, y, xa, steps, warmup)
     ktimes = kernel_times(plan, x, y, xa, steps)
-    sec_graph = time_graph_pairs(plan, x, y, xa, steps, warmup)
+    sec_graph = None if no_graph else time_graph_pairs(plan, x, y, xa, steps, warmup)
     alg = algorithmic_bytes(N, K, M, J)
     info = plan.info()
     plan.close()
@@ -197,7 +208,7 @@ def bench_2d(dev, steps, warmup, orc_mod, tune=True):
                 J=J, info=info, tuned=tuned)
 
 
-def bench_3d(dev, steps, warmup, orc_mod, tune=True):
+def bench_3d(dev, steps, warmup, orc_mod, tune="cache"):
     import torch
     from paper_1710_03197_amd import Plan, data
     c = data.config3()
@@ -310,7 +321,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="time the built-in defaults, skip the autotuner")
+    ap.add_argument("--tune", choices=["cache", "now", "off"], default="cache",
+                    help="plan options: the shipped tuning cache, tune in this run, or built-in defaults")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="after timing, copy this many MiB device to device (a plain copy of known size "
+                         "for scaling FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -326,19 +342,20 @@ def main():
     dev = torch.device("cuda:0")
     khash = kernels_hash()
 
-    r2 = bench_2d(dev, args.steps, args.warmup, orc_mod, tune=not args.no_tune)
-    dom, roof = roofline_entry(r2["ktimes"], r2["alg"], khash)
+    r2 = bench_2d(dev, args.steps, args.warmup, orc_mod, tune=args.tune, no_graph=args.no_graph)
+    dom, roof = roofline_entry(r2["ktimes"], r2["alg"], khash, "2d_256_golden_radial",
+                               (r2["tuned"] or {}).get("options"))
     extra = {
         "rel_err_forward": r2["err_f"], "rel_err_adjoint": r2["err_a"],
         "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r2["ktimes"].items()},
-        "graph_replay_pairs_per_s": round(1.0 / r2["sec_graph"], 2),
+        "graph_replay_pairs_per_s": None if r2["sec_graph"] is None else round(1.0 / r2["sec_graph"], 2),
         "pair_bytes_model": int(sum(r2["alg"].values())),
         "pair_model_frac": round(sum(r2["alg"].values()) / r2["sec"] / 1e9 / HBM_PEAK_GBS, 4),
         "plan": r2["info"], "kernels_sha": khash, "tuning": r2["tuned"],
     }
     if not args.no_3d:
-        r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod, tune=not args.no_tune)
-        _, roof3 = roofline_entry(r3["ktimes"], r3["alg"], khash)
+        r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod, tune=args.tune)
+        _, roof3 = roofline_entry(r3["ktimes"], r3["alg"], khash, "3d_128_koosh", (r3["tuned"] or {}).get("options"))
         extra["3d_128"] = {
             "pairs_per_s": round(1.0 / r3["sec"], 2), "ms_per_pair": round(r3["sec"] * 1e3, 4),
             "rel_err_forward": r3["err_f"],
@@ -351,6 +368,14 @@ def main():
     if not args.no_batched:
         extra["batched_vs_looped"] = bench_batched(dev, max(3, args.steps // 40), 2, orc_mod)
     cpu = None if args.no_cpu else cpu_baseline(orc_mod, args.cpu_seconds)
+    if args.calibration_copy_mb > 0:
+        n = args.calibration_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        extra["calibration_copy_bytes"] = n * 4
 
     result = {
         "metric": METRIC,

@@ -165,3 +165,29 @@ def tuned_plan(om: torch.Tensor, N, K=None, J: int = 6, coils=None, path: str | 
     if opts is None and tune_if_missing:
         opts = tune(om, N, K, J, path=path)["options"]
     return Plan(om, N, K, J, coils=coils, options=opts)
+
+
+SHIPPED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+
+
+def _main():
+    """Tune the benchmark workloads and write the cache:
+    python -m paper_1710_03197_amd.autotune --out FILE [--configs 2 3]"""
+    import argparse
+    from . import data
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--configs", nargs="*", type=int, default=[1, 2, 3])
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    makers = {1: data.config1, 2: data.config2, 3: data.config3}
+    dev = torch.device("cuda:0")
+    for k in args.configs:
+        c = makers[k]()
+        om = torch.from_numpy(c["om"]).to(dev)
+        res = tune(om, c["N"], c["K"], c["J"], reps=args.reps, path=args.out, verbose=True)
+        print(f"config {k}: {res}", flush=True)
+
+
+if __name__ == "__main__":
+    _main()
