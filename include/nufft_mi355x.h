@@ -86,12 +86,23 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *   grid_chunk    samples per gridding work item (>= 64)
  *   fft_groups    workgroups the FFT passes aim to launch (sets lines or
  *                 columns per workgroup)
+ *   interp_direct 1: the interpolation reads taps straight from the grid
+ *                 (through the caches) instead of staging tile + halo in LDS
+ *   presort       1: the gridding reads the samples after one permute into
+ *                 the plan's sorted order; 2: through the permutation;
+ *                 0: the default (1 for d = 3, 2 otherwise)
+ *   fuse_reduce   1: the partial tiles of split gridding tiles are summed by
+ *                 the first inverse FFT pass; 2: by a kernel of their own;
+ *                 0: the default (1 for d = 3, 2 otherwise; always 2 for d = 1)
+ * Other values give NUFFT_ERR_INVALID_ARG.
  * Used by the autotuner (paper_1710_03197_amd/autotune.py). */
 typedef struct {
     int tile[3];
     int grid_chunk;
     int fft_groups;
-    int reserved[3];
+    int interp_direct;
+    int presort;
+    int fuse_reduce;
 } nufft_options_t;
 
 /* nufft_plan with tuning options (opt may be NULL = defaults). */

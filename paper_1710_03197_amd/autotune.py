@@ -1,8 +1,11 @@
 """Autotuner for the NUFFT plan's launch parameters.
 
 Chooses, per workload, the grid tile shape used for binning, gathering and
-gridding, the number of samples per gridding work item, and how many
-workgroups the FFT passes aim for (lines or columns per workgroup).  These
+gridding, the number of samples per gridding work item, whether the gather
+stages tiles in LDS or reads the grid directly, whether the gridding reads the
+samples pre-permuted into sorted order, how many workgroups the FFT passes aim
+for (lines or columns per workgroup), and whether the first inverse FFT pass
+sums the partial tiles of split gridding tiles.  These
 change only speed: every candidate's forward and adjoint outputs must agree
 with the default plan's to 1e-5 (relative L2) before it may win, and the
 default plan is the one the parity tests hold to the FP64 oracle.
@@ -121,7 +124,21 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
                 print(f"[tune] {opts}: sample stages {t:.4f} ms", flush=True)
             if t < best_t:
                 best, best_t = opts, t
-    # 2) FFT workgroup target with that tiling, timed on the whole pair
+    # 2) the gather reading the grid directly instead of staging tiles in LDS,
+    #    and the gridding's samples pre-permuted into sorted order or read
+    #    through the permutation
+    for extra in (dict(interp_direct=1), dict(presort=1), dict(presort=2)):
+        opts = dict(best, **extra)
+        p = Plan(om, N, K, J, options=opts)
+        tried += 1
+        if valid(p):
+            t = sample_stage_time(p)
+            if verbose:
+                print(f"[tune] {opts}: sample stages {t:.4f} ms", flush=True)
+            if t < best_t:
+                best, best_t = opts, t
+        p.close()
+    # 3) FFT workgroup target with that tiling, timed on the whole pair
     best_pair, best_pt = dict(best), float("inf")
     for groups in FFT_GROUP_CANDIDATES:
         opts = dict(best, fft_groups=groups)
@@ -136,6 +153,19 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
             print(f"[tune] {opts}: pair {t:.4f} ms", flush=True)
         if t < best_pt:
             best_pair, best_pt = opts, t
+    # 4) split tiles' partial sums in the first inverse FFT pass or apart
+    if d >= 2:
+        for fuse in (1, 2):
+            opts = dict(best_pair, fuse_reduce=fuse)
+            p = Plan(om, N, K, J, options=opts)
+            tried += 1
+            if valid(p):
+                t = pair_time(p)
+                if verbose:
+                    print(f"[tune] {opts}: pair {t:.4f} ms", flush=True)
+                if t < best_pt:
+                    best_pair, best_pt = opts, t
+            p.close()
     result = {"options": {k: list(v) if isinstance(v, tuple) else v for k, v in best_pair.items()},
               "ms_pair": best_pt, "default_ms_pair": default_ms, "tried": tried}
     if save:

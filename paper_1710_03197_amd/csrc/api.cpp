@@ -115,10 +115,13 @@ struct nufft_plan_s {
     InterpItem *iitems = nullptr;  // nullptr: the gather reads the grid directly
     int64_t n_iitems = 0;
     bool staged_interp = true;
+    bool presort = false;      // gridding reads samples permuted into sorted order
+    bool fuse_reduce = false;  // first inverse FFT pass sums the partial tiles
     int seg_len = 16, segs = 1;
     int group_lanes = 64;
     int stage_floats = 0;
     HotTile *hot = nullptr;
+    int *hot_of_tile = nullptr;  // [nbins]: index into hot, or -1
     int64_t n_hot = 0;
     int64_t n_slots = 0;
     // coils
@@ -131,6 +134,7 @@ struct nufft_plan_s {
     float2 *grid = nullptr;
     float2 *tmp = nullptr;
     float2 *partials = nullptr;
+    float2 *ysorted = nullptr;  // [cap_grids][M] samples in sorted order for the gridding
     hipStream_t last_stream = nullptr;
     // optional per-kernel event timing
     bool timing = false;
@@ -167,10 +171,12 @@ int check_plan(nufft_plan_t p) {
     return NUFFT_OK;
 }
 
-enum KernelId { kFirstPass, kStridedFwd, kStridedInv, kLastPass, kInterp, kGrid, kReduce, kGrad, kNumKernels };
+enum KernelId {
+    kFirstPass, kStridedFwd, kStridedInv, kLastPass, kInterp, kGrid, kReduce, kGrad, kPermute, kNumKernels
+};
 const char *const kKernelNames[kNumKernels] = {"k_first_pass", "k_strided_pass<fwd>", "k_strided_pass<inv>",
                                                "k_last_pass", "k_interp", "k_grid", "k_reduce_partials",
-                                               "k_grad"};
+                                               "k_grad", "k_permute_samples"};
 
 hipError_t take_event(nufft_plan_s *p, hipEvent_t *ev) {
     if (!p->event_pool.empty()) {
@@ -221,10 +227,12 @@ void free_plan(nufft_plan_s *p) {
     dfree(p->items);
     dfree(p->iitems);
     dfree(p->hot);
+    dfree(p->hot_of_tile);
     dfree(p->coils);
     dfree(p->grid);
     dfree(p->tmp);
     dfree(p->partials);
+    dfree(p->ysorted);
 }
 
 // Tile edge on one axis: the largest divisor of K that is <= target, raised
@@ -366,11 +374,15 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         std::stable_sort(iitems.begin(), iitems.end(),
                          [](const InterpItem &x, const InterpItem &y) { return x.count > y.count; });
     }
+    std::vector<int> hot_of_tile(size_t(p->nbins), -1);
+    for (size_t q = 0; q < hot.size(); ++q) hot_of_tile[size_t(hot[q].tile)] = int(q);
     dfree(p->sub_start);
     dfree(p->items);
     dfree(p->iitems);
     dfree(p->hot);
+    dfree(p->hot_of_tile);
     HIP_TRY(upload(&p->sub_start, start), "upload bin offsets");
+    HIP_TRY(upload(&p->hot_of_tile, hot_of_tile), "upload split-tile index");
     HIP_TRY(upload(&p->items, items), "upload gridding work items");
     HIP_TRY(upload(&p->hot, hot), "upload split tiles");
     p->n_items = int64_t(items.size());
@@ -391,9 +403,12 @@ int ensure_workspace(nufft_plan_s *p, int grids) {
     if (g > p->cap_grids) {
         dfree(p->grid);
         dfree(p->tmp);
+        dfree(p->ysorted);
         p->cap_grids = 0;
         HIP_TRY(dmalloc(&p->grid, size_t(g) * p->grid_elems), "allocate grid workspace");
         HIP_TRY(dmalloc(&p->tmp, size_t(g) * std::max<int64_t>(p->tmp_elems, 1)), "allocate pass workspace");
+        if (p->presort)
+            HIP_TRY(dmalloc(&p->ysorted, size_t(g) * std::max<int64_t>(p->M, 1)), "allocate sorted samples");
     }
     dfree(p->partials);
     p->cap_slots = -1;
@@ -458,8 +473,10 @@ int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) 
     return NUFFT_OK;
 }
 
-// x = S^H F^H h (coil-combined): h [B*C][K^d] -> x [B][N^d].
-int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s) {
+// x = S^H F^H h (coil-combined): h [B*C][K^d] -> x [B][N^d].  With
+// fused_partials, h's split tiles are still partial tiles (run_vh with
+// reduce = false) and the first pass sums them.
+int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s, bool fused_partials = false) {
     const int d = p->d;
     const int C = p->coil_mode ? p->C : 1;
     const int64_t grids = int64_t(B) * C;
@@ -502,6 +519,19 @@ int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s) 
             a.grids = grids;
             a.inverse = true;
             a.target_groups = p->fft_groups;
+            if (ax == 0 && fused_partials && p->n_hot > 0) {
+                a.hot_of_tile = p->hot_of_tile;
+                a.hot = p->hot;
+                a.partials = p->partials;
+                a.n_slots = p->n_slots;
+                a.tile_cells = p->tile_cells;
+                a.d = d;
+                for (int b = 0; b < d; ++b) {
+                    a.Kax[b] = int(p->K[b]);
+                    a.T[b] = p->T[b];
+                    a.nt[b] = p->nt[b];
+                }
+            }
             HIP_TRY(timed(p, kStridedInv, s, [&] { return launch_strided_pass(a, s); }), "adjoint strided FFT pass");
             cur = dst;
         }
@@ -529,7 +559,12 @@ int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s)
     return NUFFT_OK;
 }
 
-int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s) {
+// reduce = false leaves split tiles as partial tiles for the first inverse FFT
+// pass to sum (d >= 2 adjoint); stage_vh and 1D reduce here.
+int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s, bool reduce = true) {
+    if (p->presort)
+        HIP_TRY(timed(p, kPermute, s, [&] { return launch_permute_samples(y, p->perm, p->M, grids, p->ysorted, s); }),
+                "sort the samples");
     GridArgs a{};
     a.geo = p->geom();
     a.om_sorted = p->om_sorted;
@@ -549,9 +584,11 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.chunk = p->chunk;
     a.items = p->items;
     a.n_items = p->n_items;
-    a.y = y;
+    a.y = p->presort ? p->ysorted : y;
+    a.y_sorted = p->presort;
     a.grids = grids;
     a.h = h;
+    a.n_kinds = segment_kinds(p->d, p->R, a.kinds);
     a.grid_elems = p->grid_elems;
     a.partials = p->partials;
     a.n_slots = p->n_slots;
@@ -571,7 +608,7 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     r.h = h;
     r.grid_elems = p->grid_elems;
     r.grids = grids;
-    if (p->n_hot > 0)
+    if (p->n_hot > 0 && reduce)
         HIP_TRY(timed(p, kReduce, s, [&] { return launch_reduce_partials(r, s); }), "gridding partial sums");
     return NUFFT_OK;
 }
@@ -929,7 +966,7 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     {
         int64_t region = sizeof(float2);
         for (int a = 0; a < d; ++a) region *= p->T[a] + J - 1;
-        p->staged_interp = region <= kLdsBudget;
+        p->staged_interp = region <= kLdsBudget && !(opt && opt->interp_direct);
     }
     if ((p->nbins << d) >= (int64_t(1) << 30)) return bail(fail(NUFFT_ERR_UNSUPPORTED, "too many bins"));
     p->chunk = d == 3 ? 1024 : 512;
@@ -939,6 +976,12 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     }
     if (opt && opt->fft_groups < 0) return bail(fail(NUFFT_ERR_INVALID_ARG, "fft_groups negative"));
     p->fft_groups = (opt && opt->fft_groups > 0) ? opt->fft_groups : 1024;
+    if (opt && (opt->presort < 0 || opt->presort > 2 || opt->fuse_reduce < 0 || opt->fuse_reduce > 2))
+        return bail(fail(NUFFT_ERR_INVALID_ARG, "presort and fuse_reduce take 0, 1 or 2"));
+    // Defaults from measurement: in 3D the gridding's dependent loads through
+    // the permutation cost more than one permute launch; in 2D they do not.
+    p->presort = (opt && opt->presort) ? opt->presort == 1 : d == 3;
+    p->fuse_reduce = d >= 2 && ((opt && opt->fuse_reduce) ? opt->fuse_reduce == 1 : d == 3);
     // intermediate sizes of the FFT passes that land in the tmp buffer
     p->tmp_elems = 1;
     for (int pass = 0; pass < d - 1; ++pass) {
@@ -1048,8 +1091,9 @@ int nufft_adjoint_batched(nufft_plan_t plan, int B, const void *y_dev, void *x_d
     const int C = plan->coil_mode ? plan->C : 1;
     if ((st = ensure_workspace(plan, B * C))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = run_vh(plan, static_cast<const float2 *>(y_dev), B * C, plan->grid, s))) return st;
-    return run_shfh(plan, plan->grid, B, static_cast<float2 *>(x_dev), s);
+    const bool fuse = plan->fuse_reduce;
+    if ((st = run_vh(plan, static_cast<const float2 *>(y_dev), B * C, plan->grid, s, !fuse))) return st;
+    return run_shfh(plan, plan->grid, B, static_cast<float2 *>(x_dev), s, fuse);
 }
 
 int nufft_forward(nufft_plan_t plan, const void *x_dev, void *y_dev, void *stream) {

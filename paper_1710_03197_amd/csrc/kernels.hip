@@ -292,7 +292,33 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
         float2 v = make_float2(0.f, 0.f);
         if (w < wv) {
             const int i = (a.Lin == K) ? q : src_row(q, a.Lin, K);
-            if (i >= 0) v = in[int64_t(i) * a.inner + w];
+            if (i >= 0) {
+                int hot = -1;
+                int cell = 0;
+                if (a.hot_of_tile) {
+                    // axis 0 row q, column c0 + w over the remaining axes
+                    int64_t c = c0 + w;
+                    int tile = 0;
+                    int kk[kMaxDim];
+                    kk[0] = q;
+                    for (int ax = a.d - 1; ax >= 1; --ax) {
+                        kk[ax] = int(c % a.Kax[ax]);
+                        c /= a.Kax[ax];
+                    }
+                    for (int ax = 0; ax < a.d; ++ax) {
+                        tile = tile * a.nt[ax] + kk[ax] / a.T[ax];
+                        cell = cell * a.T[ax] + kk[ax] % a.T[ax];
+                    }
+                    hot = a.hot_of_tile[tile];
+                }
+                if (hot < 0) {
+                    v = in[int64_t(i) * a.inner + w];
+                } else {
+                    const HotTile ht = a.hot[hot];
+                    const float2 *pp = a.partials + (g * a.n_slots + ht.slot) * a.tile_cells + cell;
+                    for (int k = 0; k < ht.nchunks; ++k) v = cadd(v, pp[int64_t(k) * a.tile_cells]);
+                }
+            }
         }
         s[e] = v;
     }
@@ -617,15 +643,35 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
             t /= a.nt[ax];
         }
     }
+    // segment bounds, one lane per segment kind (independent loads)
+    if (threadIdx.x < a.n_kinds) {
+        const int kind = a.kinds[threadIdx.x];
+        int bin = 0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            int b = tc[ax] - ((kind >> ax) & 1);
+            if (b < 0) b += a.nt[ax];
+            bin = bin * a.nt[ax] + b;
+        }
+        const int code = (kind >> 8) & 255;
+        const int base = bin << DIM;
+        if (code == 255) {
+            seg_lo[threadIdx.x] = a.sub_start[base];
+            seg_hi[threadIdx.x] = a.sub_start[base + (1 << DIM)];
+        } else {
+            seg_lo[threadIdx.x] = a.sub_start[base + code];
+            seg_hi[threadIdx.x] = a.sub_start[base + code + 1];
+        }
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const int n = tile_segments(DIM, tc, a.nt, a.R, a.sub_start, seg_lo, seg_hi);
         int pre = 0;
-        for (int q = 0; q < n; ++q) {
+        for (int q = 0; q < a.n_kinds; ++q) {
             seg_pre[q] = pre;
             pre += seg_hi[q] - seg_lo[q];
         }
-        seg_pre[n] = pre;
-        nseg_s = n;
+        seg_pre[a.n_kinds] = pre;
+        nseg_s = a.n_kinds;
     }
     __syncthreads();
     const int nseg = nseg_s;
@@ -713,7 +759,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                 }
                 wr4[c4 >> 2] = make_float4(r[0], r[1], r[2], r[3]);
             }
-            const float2 v = y[a.perm[i]];
+            const float2 v = a.y_sorted ? y[i] : y[a.perm[i]];
             sv[lane] = v.x;
             sv[BP + lane] = v.y;
         }
@@ -938,6 +984,14 @@ __global__ __launch_bounds__(256) void k_bin_keys(BinArgs a) {
 __global__ void k_iota(int *v, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) v[i] = int(i);
+}
+
+__global__ __launch_bounds__(256) void k_permute_samples(const float2 *y, const int *perm, int64_t M, int grids,
+                                                         float2 *ys) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int64_t m = perm[i];
+    for (int g = 0; g < grids; ++g) ys[int64_t(g) * M + i] = y[int64_t(g) * M + m];
 }
 
 __global__ void k_permute_points(const float *om, const int *perm, int64_t M, int d, float *out) {
@@ -1175,6 +1229,13 @@ hipError_t launch_bin_keys(const BinArgs &a, hipStream_t s) {
 hipError_t launch_iota(int *v, int64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_iota, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_samples(const float2 *y, const int *perm, int64_t M, int grids, float2 *ys,
+                                  hipStream_t s) {
+    if (M == 0 || grids == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_samples, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, y, perm, M, grids, ys);
     return hipGetLastError();
 }
 

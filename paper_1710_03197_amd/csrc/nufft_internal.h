@@ -79,6 +79,7 @@ hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s);
 
 // Pass along a strided axis: [G][outer][Lin][inner] -> [G][outer][Lout][inner],
 // Lin < K means zero padded input rows, Lout < K a cropped output.
+struct HotTile;
 struct StridedPassArgs {
     const float2 *in;
     float2 *out;
@@ -89,6 +90,17 @@ struct StridedPassArgs {
     int64_t grids;
     bool inverse;
     int target_groups;
+    // First inverse pass of the adjoint only (hot_of_tile != nullptr): cells of
+    // split gridding tiles are read as the sum of their partial tiles.
+    const int *hot_of_tile;  // [tiles] index into hot, or -1
+    const HotTile *hot;
+    const float2 *partials;  // [grids][n_slots][tile_cells]
+    int64_t n_slots;
+    int tile_cells;
+    int d;
+    int Kax[kMaxDim];
+    int T[kMaxDim];
+    int nt[kMaxDim];
 };
 hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s);
 
@@ -178,14 +190,47 @@ struct GridArgs {
     int chunk;  // samples per work item
     const GridItem *items;
     int64_t n_items;
-    const float2 *y;      // [grids][M] caller order
+    const float2 *y;      // [grids][M]: sorted sample order when y_sorted (k_permute_samples
+                          // wrote it), else the caller's order, read through perm
+    int y_sorted;
     int grids;
     float2 *h;            // [grids][K^d]
+    int n_kinds;          // segment kinds: bits 0..2 = neighbour offset e per axis,
+    int kinds[kMaxNeighbors];  // bits 8..15 = crossing code, 255 = the whole bin
     int64_t grid_elems;
     float2 *partials;     // [grids][n_slots][tile_cells]
     int64_t n_slots;
 };
 hipError_t launch_grid(const GridArgs &a, hipStream_t s);
+// ys[g][i] = y[g][perm[i]]: samples into the plan's sorted order.
+hipError_t launch_permute_samples(const float2 *y, const int *perm, int64_t M, int grids, float2 *ys,
+                                  hipStream_t s);
+
+// The segment kinds of tile_segments in the same order, as a table the
+// gridding kernel expands with one lane per segment.
+inline int segment_kinds(int d, const int *R, int *kinds) {
+    const int ncode = 1 << d;
+    int n = 0;
+    int e[kMaxDim] = {0, 0, 0};
+    while (true) {
+        int emask = 0;
+        for (int a = 0; a < d; ++a) emask |= e[a] << a;
+        if (emask == 0) {
+            kinds[n++] = 255 << 8;
+        } else {
+            for (int c = 0; c < ncode; ++c)
+                if ((c & emask) == emask) kinds[n++] = emask | (c << 8);
+        }
+        int a = d - 1;
+        while (a >= 0) {
+            if (++e[a] < R[a]) break;
+            e[a] = 0;
+            --a;
+        }
+        if (a < 0) break;
+    }
+    return n;
+}
 
 // Sorted-sample segments [lo, hi) whose windows reach tile tc: the whole own
 // bin, and from each lower neighbour bin (tc - e, e in {0,1}^d, e_a < R_a)

@@ -64,6 +64,9 @@ class Plan:
             opt.tile[a] = int(t)
         opt.grid_chunk = int(self.options.get("grid_chunk", 0))
         opt.fft_groups = int(self.options.get("fft_groups", 0))
+        opt.interp_direct = int(bool(self.options.get("interp_direct", 0)))
+        opt.presort = int(self.options.get("presort", 0))
+        opt.fuse_reduce = int(self.options.get("fuse_reduce", 0))
         with torch.cuda.device(self.device):
             _lib.call("nufft_plan_ex", d, n_arr, k_arr, self.J, self.M,
                       _ptr(om) if self.M else ctypes.c_void_p(), ctypes.byref(opt), _stream(self.device),

@@ -271,3 +271,31 @@ def test_pair_captured_in_a_graph_replays_exactly(dev):
         assert np.array_equal(y.cpu().numpy(), y_ref), k
         assert np.array_equal(xa.cpu().numpy(), x_ref), k
     p.close()
+
+
+OPTION_CASES = [
+    ((64, 64), dict(tile=(16, 16), grid_chunk=256, fft_groups=256)),
+    ((64, 64), dict(tile=(64, 8), grid_chunk=2048, fft_groups=4096, interp_direct=1)),
+    ((64, 64), dict(tile=(16, 32), grid_chunk=64, presort=1, fuse_reduce=1)),
+    ((16, 16, 16), dict(tile=(4, 4, 16), grid_chunk=2048, fft_groups=2048)),
+    ((16, 16, 16), dict(tile=(16, 8, 8), grid_chunk=128, interp_direct=1, presort=2, fuse_reduce=2)),
+    ((16, 16, 16), dict(tile=(8, 8, 8), grid_chunk=64, presort=2, fuse_reduce=1)),
+    ((64,), dict(tile=(16,), grid_chunk=64, presort=1, fuse_reduce=1)),
+]
+
+
+@pytest.mark.parametrize("N,opts", OPTION_CASES, ids=[str(i) for i in range(len(OPTION_CASES))])
+def test_tuning_options_keep_parity(orc, dev, N, opts):
+    """Every knob the autotuner turns gives the same operator."""
+    from paper_1710_03197_amd import Plan
+    K = tuple(2 * n for n in N)
+    om = {1: lambda: data.perturb(np.linspace(-np.pi, np.pi, 3000, endpoint=False)[:, None].astype(np.float32),
+                                  (128,), np.random.default_rng(9)),
+          2: lambda: data.radial_2d(48, 128), 3: lambda: data.koosh_ball_3d(96, 32)}[len(N)]()
+    x = _rand_c(N, 7)
+    yin = _rand_c((om.shape[0],), 8)
+    print(f"N={N} options={opts}", flush=True)
+    with Plan(_t(om, dev), N, K, 6, options=opts) as p:
+        assert rel_l2(_np(p.forward(_t(x, dev))), orc.forward(x, om, N, K, 6)) < TOL
+        assert rel_l2(_np(p.adjoint(_t(yin, dev))), orc.adjoint(yin, om, N, K, 6)) < TOL
+        assert rel_l2(_np(p.stage_vh(_t(yin, dev))), orc.grid(yin, om, N, K, 6)) < TOL
