@@ -104,6 +104,8 @@ struct nufft_plan_s {
     float *scale[kMaxDim] = {nullptr, nullptr, nullptr};
     float2 *tw[kMaxDim] = {nullptr, nullptr, nullptr};
     float *coef[kMaxDim] = {nullptr, nullptr, nullptr};
+    int nq[kMaxDim] = {0, 0, 0};
+    int nq_d[kMaxDim] = {0, 0, 0};
     float *dcoef[kMaxDim] = {nullptr, nullptr, nullptr};
     // trajectory and binning
     float *om = nullptr;
@@ -149,11 +151,12 @@ struct nufft_plan_s {
         SampleGeom g{};
         g.d = d;
         g.J = J;
+        g.jp = coef_row_width(J);
         for (int a = 0; a < d; ++a) {
             g.K[a] = int(K[a]);
             g.C[a] = double(K[a]) / (2.0 * kPi);
-            g.deg[a] = ker[a].deg;
-            g.deg_d[a] = ker[a].deg_d;
+            g.nq[a] = nq[a];
+            g.nq_d[a] = nq_d[a];
             g.coef[a] = coef[a];
             g.dcoef[a] = dcoef[a];
         }
@@ -929,8 +932,10 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         hipError_t e;
         if ((e = upload(&p->scale[a], kb_scaling(int(N[a]), int(K[a]), J, p->ker[a].beta))) != hipSuccess ||
             (e = upload(&p->tw[a], twiddles(int(K[a])))) != hipSuccess ||
-            (e = upload(&p->coef[a], p->ker[a].coef)) != hipSuccess ||
-            (e = upload(&p->dcoef[a], p->ker[a].dcoef)) != hipSuccess) {
+            (e = upload(&p->coef[a], coef_rows(p->ker[a].coef, J, p->ker[a].deg, coef_row_width(J), &p->nq[a]))) !=
+                hipSuccess ||
+            (e = upload(&p->dcoef[a], coef_rows(p->ker[a].dcoef, J, p->ker[a].deg_d, coef_row_width(J),
+                                                &p->nq_d[a]))) != hipSuccess) {
             st = hip_fail(e, "upload plan constants");
             return bail(st);
         }

@@ -174,6 +174,18 @@ void kb_eval_fit(const AxisKernel &k, int J, float f, float *w, float *dw) {
     }
 }
 
+std::vector<float> coef_rows(const std::vector<float> &coef, int J, int deg, int jp, int *nq) {
+    const int rows = (deg + 1 + 3) / 4 * 4;
+    std::vector<float> out(size_t(rows) * jp, 0.0f);
+    for (int r = 0; r < rows; ++r) {
+        const int q = rows - 1 - r;
+        if (q > deg) continue;
+        for (int j = 0; j < J; ++j) out[size_t(r) * jp + j] = coef[size_t(j) * (deg + 1) + q];
+    }
+    *nq = rows;
+    return out;
+}
+
 std::vector<float> kb_scaling(int N, int K, int J, double beta) {
     std::vector<float> s(N);
     for (int i = 0; i < N; ++i) s[i] = float(1.0 / kb_ft(double(i - N / 2) / K, J, beta));

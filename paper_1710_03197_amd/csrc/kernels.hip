@@ -406,17 +406,35 @@ __device__ __forceinline__ float window_pos(const SampleGeom &geo, int ax, float
     return f;
 }
 
-// w_j(f): per-tap polynomial in z = 2f - 1 (Horner, float32).
-template <int J>
-__device__ __forceinline__ void window_weights(const float *__restrict__ coef, int deg, float f, float *w) {
-    const float z = 2.0f * f - 1.0f;
+// Per-tap polynomials of the kernel fit: NJ Horner chains in z over the
+// coefficient rows (highest degree first, zero padded to a multiple of 4
+// rows).  The table is the same for every lane, so it is read through the
+// constant address space, which the compiler serves with scalar loads; a row
+// block of 4 is fetched at once instead of one dependent load per step.
+typedef const __attribute__((address_space(4))) float const_float;
+
+template <int NJ>
+__device__ __forceinline__ void poly_rows(const float *rows, int jp, int nq, float z, float *w) {
+    const_float *r = (const_float *)rows;
+    float v[NJ];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const float *c = coef + j * (deg + 1);
-        float v = c[deg];
-        for (int q = deg - 1; q >= 0; --q) v = fmaf(v, z, c[q]);
-        w[j] = v;
+    for (int j = 0; j < NJ; ++j) v[j] = 0.f;
+    for (int q = 0; q < nq; q += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) v[j] = fmaf(v[j], z, r[(q + u) * jp + j]);
+        }
     }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) w[j] = v[j];
+}
+
+// w_j(f), j < J: the kernel weights of the window whose first tap is at
+// fractional offset f.
+template <int J>
+__device__ __forceinline__ void window_weights(const SampleGeom &geo, const float *rows, int nq, float f, float *w) {
+    poly_rows<J>(rows, geo.jp, nq, 2.0f * f - 1.0f, w);
 }
 
 // ------------------------------------------------------------ work distribution
@@ -465,7 +483,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
             for (int ax = 0; ax < DIM; ++ax) {
                 int kk[J];
                 const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk);
-                window_weights<J>(a.geo.coef[ax], a.geo.deg[ax], f, w[k][ax]);
+                window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[k][ax]);
                 o = o * E[ax] + (kk[0] - base[ax]);
             }
             off[k] = o;
@@ -539,7 +557,7 @@ __global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) {
         const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk[ax]);
-        window_weights<J>(a.geo.coef[ax], a.geo.deg[ax], f, w[ax]);
+        window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[ax]);
     }
     const int64_t m = a.perm[i];
     for (int g = 0; g < a.grids; ++g) {
@@ -606,7 +624,7 @@ __device__ __forceinline__ void group_sync(int gsize) {
     }
 }
 
-template <int DIM, int LS>
+template <int DIM, int LS, int JP>
 __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     extern __shared__ float4 stage_mem[];  // float4: 16-byte aligned rows for the vector reads
     float *stage = reinterpret_cast<float *>(stage_mem);
@@ -711,7 +729,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
             int sg = 0;
             while (sg + 1 < nseg && seg_pre[sg + 1] <= f) ++sg;
             const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
-            float wl_row[kMaxJ];  // last-axis weights, spread on the row below
+            float wl_row[JP];  // last-axis weights, spread on the row below
             int o_last = 0;
 #pragma unroll
             for (int ax = 0; ax < DIM; ++ax) {
@@ -724,16 +742,15 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                 int o = int(kw) - base[ax];
                 if (a.nt[ax] > 1 && o >= a.T[ax]) o -= K;  // window wrapping in from the top
                 const float z = 2.0f * fr - 1.0f;
-                const float *coef = a.geo.coef[ax];
-                const int deg = a.geo.deg[ax];
-                for (int j = 0; j < J; ++j) {
-                    const float *cj = coef + j * (deg + 1);
-                    float v = cj[deg];
-                    for (int q = deg - 1; q >= 0; --q) v = fmaf(v, z, cj[q]);
-                    if (ax < DIM - 1) {
-                        sw[(ax * J + j) * BP + lane] = v;
-                    } else if (j < kMaxJ) {
-                        wl_row[j] = v;
+                float wv[JP];
+                poly_rows<JP>(a.geo.coef[ax], JP, a.geo.nq[ax], z, wv);
+#pragma unroll
+                for (int j = 0; j < JP; ++j) {
+                    if (j < J) {
+                        if (ax < DIM - 1)
+                            sw[(ax * J + j) * BP + lane] = wv[j];
+                        else
+                            wl_row[j] = wv[j];
                     }
                 }
                 if (ax < DIM - 1) so[ax * BP + lane] = o;
@@ -753,7 +770,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                     if (wrapl && j < 0) j += Kl;
                     float v = 0.f;
 #pragma unroll
-                    for (int jj = 0; jj < kMaxJ; ++jj)
+                    for (int jj = 0; jj < JP; ++jj)
                         if (jj < J && j == jj) v = wl_row[jj];
                     r[u] = (c4 + u < L) ? v : 0.f;
                 }
@@ -887,8 +904,8 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs a) {
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) {
         const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk[ax]);
-        window_weights<J>(a.geo.coef[ax], a.geo.deg[ax], f, w[ax]);
-        window_weights<J>(a.geo.dcoef[ax], a.geo.deg_d[ax], f, dw[ax]);
+        window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[ax]);
+        window_weights<J>(a.geo, a.geo.dcoef[ax], a.geo.nq_d[ax], f, dw[ax]);
     }
     const int64_t m = a.perm[i];
     float gsum[DIM];
@@ -1184,7 +1201,13 @@ hipError_t launch_interp(const InterpArgs &a, hipStream_t s) {
 template <int DIM, int LS>
 hipError_t launch_grid_t(const GridArgs &a, hipStream_t s) {
     const size_t lds = size_t(kGridThreads / a.group_lanes) * a.stage_floats * sizeof(float);
-    hipLaunchKernelGGL((k_grid<DIM, LS>), dim3(unsigned(a.n_items), unsigned(a.grids)), dim3(kGridThreads), lds, s, a);
+    const dim3 grid(unsigned(a.n_items), unsigned(a.grids));
+    if (a.geo.jp == 8)
+        hipLaunchKernelGGL((k_grid<DIM, LS, 8>), grid, dim3(kGridThreads), lds, s, a);
+    else if (a.geo.jp == 16)
+        hipLaunchKernelGGL((k_grid<DIM, LS, 16>), grid, dim3(kGridThreads), lds, s, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

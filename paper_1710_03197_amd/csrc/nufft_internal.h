@@ -49,6 +49,14 @@ double kb_ft(double xi, int J, double beta);       // continuous Fourier transfo
 bool kb_fit(int J, double beta, AxisKernel *out);
 // Evaluate the fitted polynomials exactly as the GPU does (float32 Horner).
 void kb_eval_fit(const AxisKernel &k, int J, float f, float *w, float *dw);
+// Device layout of per-tap coefficients [J][deg+1]: rows r = 0..nq-1 of jp
+// floats, row r holding the degree nq-1-r coefficient of every tap (zero for
+// degrees above deg and taps j >= J), nq = deg+1 rounded up to a multiple of
+// 4.  Horner from v = 0 over the rows gives the same float32 result as over
+// the unpadded coefficients (the leading zero rows keep v at 0).
+std::vector<float> coef_rows(const std::vector<float> &coef, int J, int deg, int jp, int *nq);
+// Row width for J taps: 8 for J <= 8, else 16.
+inline int coef_row_width(int J) { return J <= 8 ? 8 : 16; }
 // Scaling table s(i) = 1 / Phi((i - N/2)/K), i in [0, N) (float32).
 std::vector<float> kb_scaling(int N, int K, int J, double beta);
 // Twiddles e^{-2 pi i e / K}, e in [0, K), computed in float64.
@@ -128,10 +136,11 @@ struct SampleGeom {
     int J;
     int K[kMaxDim];
     double C[kMaxDim];   // K_a / (2 pi)
-    int deg[kMaxDim];
-    int deg_d[kMaxDim];
-    const float *coef[kMaxDim];   // [J][deg+1]
-    const float *dcoef[kMaxDim];  // [J][deg_d+1]
+    int jp;               // coefficient row width (coef_row_width(J))
+    int nq[kMaxDim];      // coefficient rows of the kernel fit (multiple of 4)
+    int nq_d[kMaxDim];    // coefficient rows of the derivative fit
+    const float *coef[kMaxDim];   // [nq][jp], highest degree first (coef_rows)
+    const float *dcoef[kMaxDim];  // [nq_d][jp]
 };
 
 // Interpolation V: y[g][perm[i]] = sum_taps w * G[g][..] for sorted sample i.
