@@ -94,6 +94,11 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *   fuse_reduce   1: the partial tiles of split gridding tiles are summed by
  *                 the first inverse FFT pass; 2: by a kernel of their own;
  *                 0: the default (1 for d = 3, 2 otherwise; always 2 for d = 1)
+ *   grid_mfma     1: gridding on the matrix cores (needs tile[d-1] = 16,
+ *                 16, 32 or 64 cells over the leading axes and a tile
+ *                 perimeter sum(tile) <= 61, else NUFFT_ERR_UNSUPPORTED);
+ *                 2: on the vector ALUs; 0: matrix cores where the tile
+ *                 allows it (d >= 2)
  * Other values give NUFFT_ERR_INVALID_ARG.
  * Used by the autotuner (paper_1710_03197_amd/autotune.py). */
 typedef struct {
@@ -103,6 +108,8 @@ typedef struct {
     int interp_direct;
     int presort;
     int fuse_reduce;
+    int grid_mfma;
+    int reserved[3];
 } nufft_options_t;
 
 /* nufft_plan with tuning options (opt may be NULL = defaults). */

@@ -19,6 +19,9 @@ FLAGS = [
     "-ffp-contract=fast",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: the AGPR form made the compiler
+    # copy loop-carried accumulators around every matrix instruction
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",
     f"-I{os.path.join(ROOT, 'include')}",
 ]

@@ -119,6 +119,8 @@ struct nufft_plan_s {
     bool staged_interp = true;
     bool presort = false;      // gridding reads samples permuted into sorted order
     bool fuse_reduce = false;  // first inverse FFT pass sums the partial tiles
+    bool grid_mfma = false;    // gridding on the matrix cores
+    int rec_stride = 0;        // its LDS floats per staged sample
     int seg_len = 16, segs = 1;
     int group_lanes = 64;
     int stage_floats = 0;
@@ -595,6 +597,8 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.grid_elems = p->grid_elems;
     a.partials = p->partials;
     a.n_slots = p->n_slots;
+    a.mfma = p->grid_mfma;
+    a.rec_stride = p->rec_stride;
     HIP_TRY(timed(p, kGrid, s, [&] { return launch_grid(a, s); }), "gridding");
     ReduceArgs r{};
     r.hot = p->hot;
@@ -967,6 +971,19 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         p->stage_floats = (p->stage_floats + 3) & ~3;  // keep every group's rows 16-byte aligned
         if (int64_t(256 / p->group_lanes) * p->stage_floats * int64_t(sizeof(float)) > kLdsBudget)
             return bail(fail(NUFFT_ERR_UNSUPPORTED, "gridding tile too large for LDS"));
+        // matrix-core gridding: tiles of 16 cells on the last axis and 16, 32
+        // or 64 rows (default where the tile allows it)
+        if (opt && (opt->grid_mfma < 0 || opt->grid_mfma > 2))
+            return bail(fail(NUFFT_ERR_INVALID_ARG, "grid_mfma takes 0, 1 or 2"));
+        int tsum = 0;
+        for (int a = 0; a < d; ++a) tsum += p->T[a];
+        p->rec_stride = (2 + tsum) | 1;  // value + the tile's coordinates per axis, odd (no bank conflicts)
+        const bool mfma_ok = d >= 2 && L == 16 && (rows == 16 || rows == 32 || rows == 64) &&
+                             int64_t(4) * 64 * p->rec_stride * int64_t(sizeof(float)) <= kLdsBudget;
+        if (opt && opt->grid_mfma == 1 && !mfma_ok)
+            return bail(fail(NUFFT_ERR_UNSUPPORTED,
+                             "matrix-core gridding needs T_last = 16, 16, 32 or 64 rows and sum(T) <= 61"));
+        p->grid_mfma = mfma_ok && !(opt && opt->grid_mfma == 2);
     }
     {
         int64_t region = sizeof(float2);

@@ -175,7 +175,7 @@ void kb_eval_fit(const AxisKernel &k, int J, float f, float *w, float *dw) {
 }
 
 std::vector<float> coef_rows(const std::vector<float> &coef, int J, int deg, int jp, int *nq) {
-    const int rows = (deg + 1 + 3) / 4 * 4;
+    const int rows = (deg + 1 + 1) / 2 * 2;
     std::vector<float> out(size_t(rows) * jp, 0.0f);
     for (int r = 0; r < rows; ++r) {
         const int q = rows - 1 - r;

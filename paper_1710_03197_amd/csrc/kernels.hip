@@ -407,10 +407,10 @@ __device__ __forceinline__ float window_pos(const SampleGeom &geo, int ax, float
 }
 
 // Per-tap polynomials of the kernel fit: NJ Horner chains in z over the
-// coefficient rows (highest degree first, zero padded to a multiple of 4
+// coefficient rows (highest degree first, zero padded to a multiple of 2
 // rows).  The table is the same for every lane, so it is read through the
 // constant address space, which the compiler serves with scalar loads; a row
-// block of 4 is fetched at once instead of one dependent load per step.
+// pair is fetched at once instead of one dependent load per step.
 typedef const __attribute__((address_space(4))) float const_float;
 
 template <int NJ>
@@ -419,9 +419,9 @@ __device__ __forceinline__ void poly_rows(const float *rows, int jp, int nq, flo
     float v[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) v[j] = 0.f;
-    for (int q = 0; q < nq; q += 4) {
+    for (int q = 0; q < nq; q += 2) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) v[j] = fmaf(v[j], z, r[(q + u) * jp + j]);
         }
@@ -624,6 +624,45 @@ __device__ __forceinline__ void group_sync(int gsize) {
     }
 }
 
+// The sorted-sample segments that reach tile `tc` (its own bin and the
+// crossing sub-bins of its lower neighbours, in segment_kinds order): bounds
+// loaded one lane per kind, then prefix sums.  Every thread of the workgroup
+// calls it; returns the number of segments.
+template <int DIM>
+__device__ __forceinline__ int grid_item_segments(const GridArgs &a, const int *tc, int *seg_lo, int *seg_hi,
+                                                  int *seg_pre) {
+    if (threadIdx.x < a.n_kinds) {
+        const int kind = a.kinds[threadIdx.x];
+        int bin = 0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            int b = tc[ax] - ((kind >> ax) & 1);
+            if (b < 0) b += a.nt[ax];
+            bin = bin * a.nt[ax] + b;
+        }
+        const int code = (kind >> 8) & 255;
+        const int base = bin << DIM;
+        if (code == 255) {
+            seg_lo[threadIdx.x] = a.sub_start[base];
+            seg_hi[threadIdx.x] = a.sub_start[base + (1 << DIM)];
+        } else {
+            seg_lo[threadIdx.x] = a.sub_start[base + code];
+            seg_hi[threadIdx.x] = a.sub_start[base + code + 1];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int pre = 0;
+        for (int q = 0; q < a.n_kinds; ++q) {
+            seg_pre[q] = pre;
+            pre += seg_hi[q] - seg_lo[q];
+        }
+        seg_pre[a.n_kinds] = pre;
+    }
+    __syncthreads();
+    return a.n_kinds;
+}
+
 template <int DIM, int LS, int JP>
 __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     extern __shared__ float4 stage_mem[];  // float4: 16-byte aligned rows for the vector reads
@@ -631,7 +670,6 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     __shared__ int seg_lo[kMaxNeighbors];
     __shared__ int seg_hi[kMaxNeighbors];
     __shared__ int seg_pre[kMaxNeighbors + 1];
-    __shared__ int nseg_s;
     const GridItem it = a.items[blockIdx.x];
     const int g = blockIdx.y;
     const int J = a.geo.J;
@@ -661,38 +699,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
             t /= a.nt[ax];
         }
     }
-    // segment bounds, one lane per segment kind (independent loads)
-    if (threadIdx.x < a.n_kinds) {
-        const int kind = a.kinds[threadIdx.x];
-        int bin = 0;
-#pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) {
-            int b = tc[ax] - ((kind >> ax) & 1);
-            if (b < 0) b += a.nt[ax];
-            bin = bin * a.nt[ax] + b;
-        }
-        const int code = (kind >> 8) & 255;
-        const int base = bin << DIM;
-        if (code == 255) {
-            seg_lo[threadIdx.x] = a.sub_start[base];
-            seg_hi[threadIdx.x] = a.sub_start[base + (1 << DIM)];
-        } else {
-            seg_lo[threadIdx.x] = a.sub_start[base + code];
-            seg_hi[threadIdx.x] = a.sub_start[base + code + 1];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int pre = 0;
-        for (int q = 0; q < a.n_kinds; ++q) {
-            seg_pre[q] = pre;
-            pre += seg_hi[q] - seg_lo[q];
-        }
-        seg_pre[a.n_kinds] = pre;
-        nseg_s = a.n_kinds;
-    }
-    __syncthreads();
-    const int nseg = nseg_s;
+    const int nseg = grid_item_segments<DIM>(a, tc, seg_lo, seg_hi, seg_pre);
     const int total = seg_pre[nseg];
     const int f0 = it.chunk * a.chunk;
     const int n = min(total, f0 + a.chunk) - f0;
@@ -862,6 +869,189 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
             }
             dst[idx] = sum;
         }
+    }
+}
+
+// V^H on the matrix cores, for tiles of 16*MB rows (the leading axes) by 16
+// cells (last axis).  Over a batch of samples s the tile is
+//   H[r][c] = sum_s (v_s * wlead_s[r]) * wlast_s[c],
+// a product of a rows x samples matrix and a samples x 16 matrix, i.e.
+// 16x16x4 fp32 MFMAs with the samples as the reduction dimension (real and
+// imaginary parts as two products sharing the wlast operand).  Each wave
+// stages 64 samples in LDS: the value and, per axis, the sample's weights
+// spread over the tile's T_a coordinates (zero outside the window, window
+// wrapping resolved here), so in the walk lane (i + 16k) reads A[i][k] and
+// B[k][i] of sample k at fixed offsets.  The four waves take different samples
+// of the item and their tiles are summed in LDS in wave order (deterministic).
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int DIM, int NJ, int MB>
+__global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
+    extern __shared__ float mf_lds[];
+    __shared__ int seg_lo[kMaxNeighbors];
+    __shared__ int seg_hi[kMaxNeighbors];
+    __shared__ int seg_pre[kMaxNeighbors + 1];
+    const GridItem it = a.items[blockIdx.x];
+    const int g = blockIdx.y;
+    const int J = a.geo.J;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+    const int lane = threadIdx.x & 63;
+    const int RS = a.rec_stride;  // floats per staged sample: v.x, v.y, then T_a weights per axis
+    float *rec = mf_lds + wave * 64 * RS;
+
+    int tc[DIM];
+    {
+        int t = it.tile;
+#pragma unroll
+        for (int ax = DIM - 1; ax >= 0; --ax) {
+            tc[ax] = t % a.nt[ax];
+            t /= a.nt[ax];
+        }
+    }
+    const int nseg = grid_item_segments<DIM>(a, tc, seg_lo, seg_hi, seg_pre);
+    const int total = seg_pre[nseg];
+    const int f0 = it.chunk * a.chunk;
+    const int n = min(total, f0 + a.chunk) - f0;
+    int base[DIM], off[DIM];
+    {
+        int o = 2;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            base[ax] = tc[ax] * a.T[ax];
+            off[ax] = o;
+            o += a.T[ax];
+        }
+    }
+
+    // this lane's record offsets: A operand (leading weights of row
+    // 16 blk + rl, per row block) and B operand (last-axis weight of column rl)
+    const int rl = lane & 15;
+    const int kq = lane >> 4;
+    int aoff[MB][DIM - 1];
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk) {
+        int r = blk * 16 + rl;
+#pragma unroll
+        for (int ax = DIM - 2; ax >= 0; --ax) {
+            aoff[blk][ax] = off[ax] + r % a.T[ax];
+            r /= a.T[ax];
+        }
+    }
+    const int boff = off[DIM - 1] + rl;
+    const float2 *y = a.y + int64_t(g) * a.M;
+    mfma_f4 acc_re[MB], acc_im[MB];
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk) {
+        acc_re[blk] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+        acc_im[blk] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    }
+    // The global reads of a batch (trajectory, sample value) are issued one
+    // batch ahead, so they are in flight while the wave walks the current one.
+    float pom[DIM];
+    float2 pv = make_float2(0.f, 0.f);
+    bool pvalid = false;
+    auto fetch = [&](int b) {
+        const int s_idx = b + wave * 64 + lane;
+        pvalid = s_idx < n;
+        if (pvalid) {
+            const int f = f0 + s_idx;
+            int sg = 0;
+            while (sg + 1 < nseg && seg_pre[sg + 1] <= f) ++sg;
+            const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) pom[ax] = a.om_sorted[i * DIM + ax];
+            pv = a.y_sorted ? y[i] : y[a.perm[i]];
+        }
+    };
+    fetch(0);
+    for (int b0 = 0; b0 < n; b0 += 256) {
+        // ---- stage: lane = sample b0 + 64 * wave + lane of the item
+        float *my = rec + lane * RS;
+        my[0] = pvalid ? pv.x : 0.f;
+        my[1] = pvalid ? pv.y : 0.f;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            float *E = my + off[ax];
+            const int T = a.T[ax];
+#pragma unroll 4
+            for (int x = 0; x < T; ++x) E[x] = 0.f;
+            if (pvalid) {
+                const double u = __dmul_rn(double(pom[ax]), a.geo.C[ax]);
+                const double k0 = floor(u - 0.5 * J) + 1.0;
+                const float fr = float(u - k0 - (0.5 * J - 1.0));
+                const int K = a.geo.K[ax];
+                long long kw = static_cast<long long>(k0) % K;
+                if (kw < 0) kw += K;
+                const int o = int(kw) - base[ax];  // first tap relative to the tile, in [-base, K - base)
+                float wv[NJ];
+                poly_rows<NJ>(a.geo.coef[ax], a.geo.jp, a.geo.nq[ax], 2.0f * fr - 1.0f, wv);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    if (j < J) {
+                        int x = o + j;
+                        if (x >= K) x -= K;  // taps wrapping past the top of the axis
+                        if (x >= 0 && x < T) E[x] = wv[j];
+                    }
+                }
+            }
+        }
+        if (b0 + 256 < n) fetch(b0 + 256);
+        group_sync(64);
+        // ---- walk: 4 samples per step
+        const int nb = min(64, n - (b0 + wave * 64));
+#pragma unroll 2
+        for (int st = 0; st * 4 < nb; ++st) {
+            const float *sr = rec + (st * 4 + kq) * RS;
+            const float vx = sr[0], vy = sr[1];
+            const float bw = sr[boff];
+#pragma unroll
+            for (int blk = 0; blk < MB; ++blk) {
+                float wl = sr[aoff[blk][0]];
+#pragma unroll
+                for (int ax = 1; ax < DIM - 1; ++ax) wl *= sr[aoff[blk][ax]];
+                acc_re[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx * wl, bw, acc_re[blk], 0, 0, 0);
+                acc_im[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy * wl, bw, acc_im[blk], 0, 0, 0);
+            }
+        }
+        group_sync(64);
+    }
+    // ---- sum the waves' tiles in wave order and write the tile
+    __syncthreads();  // every wave is done with its staging area
+    const int cells = MB * 256;
+    float2 *red = reinterpret_cast<float2 *>(mf_lds);  // [4][cells], reuses the staging LDS
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = blk * 16 + 4 * kq + q;  // D[row][col] sits in lane col + 16 (row / 4), register row % 4
+            red[wave * cells + row * 16 + rl] = make_float2(acc_re[blk][q], acc_im[blk][q]);
+        }
+    }
+    __syncthreads();
+    const bool to_partial = it.nchunks > 1;
+    float2 *dst = to_partial ? a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells
+                             : a.h + int64_t(g) * a.grid_elems;
+    for (int e = threadIdx.x; e < cells; e += 256) {
+        float2 sum = red[e];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) sum = cadd(sum, red[q * cells + e]);
+        int64_t idx;
+        if (to_partial) {
+            idx = e;
+        } else {
+            int rr = e >> 4;
+            int l[DIM];
+            l[DIM - 1] = e & 15;
+#pragma unroll
+            for (int ax = DIM - 2; ax >= 0; --ax) {
+                l[ax] = rr % a.T[ax];
+                rr /= a.T[ax];
+            }
+            idx = 0;
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) idx = idx * a.geo.K[ax] + base[ax] + l[ax];
+        }
+        dst[idx] = sum;
     }
 }
 
@@ -1221,8 +1411,38 @@ hipError_t launch_grid_d(const GridArgs &a, hipStream_t s) {
     }
 }
 
+template <int DIM, int NJ>
+hipError_t launch_grid_mfma_j(const GridArgs &a, hipStream_t s) {
+    const int cells = a.tile_cells;
+    const size_t lds = std::max(size_t(4) * 64 * a.rec_stride, size_t(4) * 2 * cells) * sizeof(float);
+    const dim3 grid(unsigned(a.n_items), unsigned(a.grids));
+    switch (cells) {
+        case 256: hipLaunchKernelGGL((k_grid_mfma<DIM, NJ, 1>), grid, dim3(256), lds, s, a); break;
+        case 512: hipLaunchKernelGGL((k_grid_mfma<DIM, NJ, 2>), grid, dim3(256), lds, s, a); break;
+        case 1024: hipLaunchKernelGGL((k_grid_mfma<DIM, NJ, 4>), grid, dim3(256), lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t launch_grid_mfma_d(const GridArgs &a, hipStream_t s) {
+    if (a.T[DIM - 1] != 16) return hipErrorInvalidValue;
+    // taps evaluated per sample: J rounded up to 6, 8 or 16
+    if (a.geo.J <= 6) return launch_grid_mfma_j<DIM, 6>(a, s);
+    if (a.geo.J <= 8) return launch_grid_mfma_j<DIM, 8>(a, s);
+    return launch_grid_mfma_j<DIM, 16>(a, s);
+}
+
 hipError_t launch_grid(const GridArgs &a, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
+    if (a.mfma) {
+        switch (a.geo.d) {
+            case 2: return launch_grid_mfma_d<2>(a, s);
+            case 3: return launch_grid_mfma_d<3>(a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.geo.d) {
         case 1: return launch_grid_d<1>(a, s);
         case 2: return launch_grid_d<2>(a, s);

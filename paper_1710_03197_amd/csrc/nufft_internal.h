@@ -52,8 +52,8 @@ void kb_eval_fit(const AxisKernel &k, int J, float f, float *w, float *dw);
 // Device layout of per-tap coefficients [J][deg+1]: rows r = 0..nq-1 of jp
 // floats, row r holding the degree nq-1-r coefficient of every tap (zero for
 // degrees above deg and taps j >= J), nq = deg+1 rounded up to a multiple of
-// 4.  Horner from v = 0 over the rows gives the same float32 result as over
-// the unpadded coefficients (the leading zero rows keep v at 0).
+// 2.  Horner from v = 0 over the rows gives the same float32 result as over
+// the unpadded coefficients (the leading zero row keeps v at 0).
 std::vector<float> coef_rows(const std::vector<float> &coef, int J, int deg, int jp, int *nq);
 // Row width for J taps: 8 for J <= 8, else 16.
 inline int coef_row_width(int J) { return J <= 8 ? 8 : 16; }
@@ -137,7 +137,7 @@ struct SampleGeom {
     int K[kMaxDim];
     double C[kMaxDim];   // K_a / (2 pi)
     int jp;               // coefficient row width (coef_row_width(J))
-    int nq[kMaxDim];      // coefficient rows of the kernel fit (multiple of 4)
+    int nq[kMaxDim];      // coefficient rows of the kernel fit (multiple of 2)
     int nq_d[kMaxDim];    // coefficient rows of the derivative fit
     const float *coef[kMaxDim];   // [nq][jp], highest degree first (coef_rows)
     const float *dcoef[kMaxDim];  // [nq_d][jp]
@@ -209,6 +209,8 @@ struct GridArgs {
     int64_t grid_elems;
     float2 *partials;     // [grids][n_slots][tile_cells]
     int64_t n_slots;
+    int mfma;             // matrix-core gridding (d >= 2, T_last = 16, 16, 32 or 64 rows)
+    int rec_stride;       // its LDS floats per staged sample: 2 + sum of T_a, made odd
 };
 hipError_t launch_grid(const GridArgs &a, hipStream_t s);
 // ys[g][i] = y[g][perm[i]]: samples into the plan's sorted order.

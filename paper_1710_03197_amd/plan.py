@@ -67,6 +67,7 @@ class Plan:
         opt.interp_direct = int(bool(self.options.get("interp_direct", 0)))
         opt.presort = int(self.options.get("presort", 0))
         opt.fuse_reduce = int(self.options.get("fuse_reduce", 0))
+        opt.grid_mfma = int(self.options.get("grid_mfma", 0))
         with torch.cuda.device(self.device):
             _lib.call("nufft_plan_ex", d, n_arr, k_arr, self.J, self.M,
                       _ptr(om) if self.M else ctypes.c_void_p(), ctypes.byref(opt), _stream(self.device),

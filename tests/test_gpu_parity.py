@@ -281,6 +281,14 @@ OPTION_CASES = [
     ((16, 16, 16), dict(tile=(16, 8, 8), grid_chunk=128, interp_direct=1, presort=2, fuse_reduce=2)),
     ((16, 16, 16), dict(tile=(8, 8, 8), grid_chunk=64, presort=2, fuse_reduce=1)),
     ((64,), dict(tile=(16,), grid_chunk=64, presort=1, fuse_reduce=1)),
+    ((64, 64), dict(tile=(16, 16), grid_mfma=2)),
+    ((64, 64), dict(tile=(32, 16), grid_chunk=128, grid_mfma=1, presort=1)),
+    ((64, 64), dict(tile=(16, 16), grid_chunk=64, grid_mfma=1, fuse_reduce=2)),
+    ((8, 8), dict(tile=(16, 16), grid_mfma=1)),                  # one tile per axis: wrapped windows
+    ((16, 16, 16), dict(tile=(8, 8, 16), grid_mfma=1, presort=2)),
+    ((16, 16, 16), dict(tile=(8, 8, 16), grid_mfma=2)),
+    ((16, 16, 16), dict(tile=(8, 8, 16), grid_chunk=64, grid_mfma=1, fuse_reduce=2)),
+    ((8, 8, 8), dict(tile=(8, 8, 16), grid_mfma=1)),              # last axis one tile
 ]
 
 
