@@ -48,6 +48,7 @@ def _load():
         getattr(lib, f).restype = ctypes.c_double
         getattr(lib, f).argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_toeplitz_conv.argtypes = [ctypes.c_int, _i64p, _dp, _dp, _dp]
     lib.orc_scaling.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _dp]
     lib.orc_fftn.argtypes = [ctypes.c_int, _i64p, _dp, ctypes.c_int]
     lib.orc_fft_axis.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, _dp, ctypes.c_int]
@@ -284,6 +285,58 @@ def loss_and_grads(x, om, coils, target_y, N, K, J):
         gx += np.conj(np.asarray(c, np.complex128)) * adjoint(gy, om, N, K, J)
         grad_points(G, gy, om, N, K, J, out=gom)
     return L, gx, gom
+
+
+# ------------------------------------------------------------------ Toeplitz normal operator
+def toeplitz_psf(om, N, K, J, w=None) -> np.ndarray:
+    """Point-spread function of A^H W A (paper Section 2.1, "Self-adjoint
+    NUFFT"): p[Delta] = sum_m w_m e^{+i omega_m . Delta} for Delta in
+    [-N, N)^d, stored centred (index Delta + N, shape 2N).  Computed the way
+    the method does: the adjoint NUFFT with image size 2N and grid 2K (same
+    oversampling and J) applied to the weights (w = 1 when None)."""
+    N2 = tuple(2 * int(n) for n in N)
+    K2 = tuple(2 * int(k) for k in K)
+    M = np.asarray(om).shape[0]
+    wv = np.ones(M) if w is None else np.asarray(w, np.float64)
+    return adjoint(wv.astype(np.complex128), om, N2, K2, J)
+
+
+def toeplitz_conv(p, x, N) -> np.ndarray:
+    """out[n] = sum_{n'} p[n - n'] x[n'] over the image (direct sum)."""
+    d = len(N)
+    pp, ppp = _c128(np.asarray(p).reshape(tuple(2 * int(n) for n in N)))
+    xx, xp = _c128(np.asarray(x).reshape(tuple(N)))
+    out = np.empty(tuple(N), dtype=np.complex128)
+    n, np_ = _shape(N)
+    _load().orc_toeplitz_conv(d, np_, ppp, xp, out.ctypes.data_as(_dp))
+    return out
+
+
+def toeplitz_conv_fft(p, x, N) -> np.ndarray:
+    """The same product through the circulant embedding: place p at
+    Delta mod 2N and x at n mod 2N, multiply the (oracle) FFTs, invert,
+    crop, divide by prod(2N).  Used where the direct sum is too slow; pinned
+    against it on small sizes."""
+    N = tuple(int(n) for n in N)
+    P = tuple(2 * n for n in N)
+    pc = np.asarray(p, np.complex128).reshape(P)
+    pm = pc
+    for a, n in enumerate(N):
+        pm = np.roll(pm, -n, axis=a)          # centred index Delta + N -> Delta mod 2N
+    xe = np.zeros(P, np.complex128)
+    xe[tuple(slice(0, n) for n in N)] = np.asarray(x, np.complex128).reshape(N)
+    for a, n in enumerate(N):
+        xe = np.roll(xe, -(n // 2), axis=a)   # image index i -> (i - N/2) mod 2N
+    z = fftn(fftn(pm, -1) * fftn(xe, -1), +1) / float(np.prod(P))
+    for a, n in enumerate(N):
+        z = np.roll(z, n // 2, axis=a)
+    return z[tuple(slice(0, n) for n in N)]
+
+
+def toeplitz_normal(x, om, N, K, J, w=None, fft: bool = False) -> np.ndarray:
+    """A^H W A x by the Toeplitz embedding (PSF from the oracle adjoint)."""
+    p = toeplitz_psf(om, N, K, J, w)
+    return (toeplitz_conv_fft if fft else toeplitz_conv)(p, x, N)
 
 
 # ------------------------------------------------------------------ CG

@@ -436,3 +436,37 @@ void orc_grad_points(int d, const int64_t *N, const int64_t *K, int J, int64_t M
         }
     }
 }
+
+/* Circulant-embedding product of the normal operator (paper Section 2.1,
+ * "Self-adjoint NUFFT": A^H A applied without the interpolator in the loop):
+ *   out[n] = sum_{n'} p[n - n'] x[n'],   n, n' in [-N/2, N/2)^d,
+ * with the point-spread function p stored centred on [-N, N)^d (array index
+ * Delta_a + N_a, shape 2N).  Plain direct sum, O(N^d * N^d). */
+void orc_toeplitz_conv(int d, const int64_t *N, const cplx *p, const cplx *x, cplx *out) {
+    int64_t nN = prod(d, N);
+    int64_t P[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) P[a] = 2 * N[a];
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < nN; ++e) {
+        int64_t i[3] = {0, 0, 0};
+        int64_t r = e;
+        for (int a = d - 1; a >= 0; --a) {
+            i[a] = r % N[a];
+            r /= N[a];
+        }
+        cplx acc = 0.0;
+        for (int64_t f = 0; f < nN; ++f) {
+            int64_t j[3] = {0, 0, 0};
+            int64_t s = f;
+            for (int a = d - 1; a >= 0; --a) {
+                j[a] = s % N[a];
+                s /= N[a];
+            }
+            /* Delta = n - n' = i - j; centred index Delta + N */
+            int64_t idx = 0;
+            for (int a = 0; a < d; ++a) idx = idx * P[a] + (i[a] - j[a] + N[a]);
+            acc += p[idx] * x[f];
+        }
+        out[e] = acc;
+    }
+}
