@@ -223,6 +223,36 @@ int nufft_multi_adjoint(nufft_multi_t m, const void *const *y_dev, void *const *
  * handle returns BAD_PLAN. */
 int nufft_multi_destroy(nufft_multi_t m);
 
+/* ---- Toeplitz normal operator (Section 2.1, "Self-adjoint NUFFT"; Table 1)
+ *
+ * out = A^H W A x applied without the interpolator: with the point-spread
+ * function p[Delta] = sum_m w_m e^{+i omega_m . Delta}, Delta in [-N, N)^d,
+ *   out[n] = sum_{n'} p[n - n'] x[n'],
+ * computed as crop(F^-1(P . F(pad(x)))) on the 2N grid, P the FFT of p
+ * divided by prod(2N).  Each application costs two zero-padded FFTs of size
+ * 2N and a product (fused into the first inverse pass), against a forward +
+ * adjoint pair through the interpolator.
+ *
+ * nufft_toeplitz_plan builds P from `plan`'s trajectory: one adjoint NUFFT
+ * with image 2N on grid 2K (same J and oversampling) of the weights, then one
+ * FFT.  w_dev: device float [M] real sample weights in the caller's sample
+ * order (density compensation), NULL for w = 1.  Synchronous on `stream`;
+ * needs 2N_a 2-3-5 smooth and <= 4096 and 2K_a <= 4096 (NUFFT_ERR_UNSUPPORTED),
+ * finite weights (NUFFT_ERR_NONFINITE).  The operator keeps a reference to
+ * `plan`: destroy the operator first; calls after the plan is gone return
+ * NUFFT_ERR_BAD_PLAN.
+ *
+ * nufft_toeplitz_apply: x_dev complex64 [B][N^d] -> out_dev complex64
+ * [B][N^d], asynchronous on `stream`.  In coil mode (the plan's coils at the
+ * time of the call) out = sum_i conj(c_i) . T(c_i . x), i.e. A_c^H W A_c with
+ * A_c the coil-mode forward.  x and out must not overlap.  The workspace
+ * grows on the first call with a larger B * C (that call allocates).
+ */
+typedef struct nufft_toeplitz_s *nufft_toeplitz_t;
+int nufft_toeplitz_plan(nufft_plan_t plan, const float *w_dev, void *stream, nufft_toeplitz_t *out);
+int nufft_toeplitz_apply(nufft_toeplitz_t t, int B, const void *x_dev, void *out_dev, void *stream);
+int nufft_toeplitz_destroy(nufft_toeplitz_t t);
+
 /* Synchronise the plan's last stream and free everything.  A NULL, destroyed
  * or foreign handle returns BAD_PLAN and is not touched. */
 int nufft_destroy(nufft_plan_t plan);

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <set>
@@ -427,50 +428,90 @@ int ensure_workspace(nufft_plan_s *p, int grids) {
 // ---- stage sequences
 
 // G = F S (c x): x [B][N^d] -> out [B*C][K^d]; intermediates in the workspace.
-int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) {
-    const int d = p->d;
-    const int C = p->coil_mode ? p->C : 1;
-    const int64_t grids = int64_t(B) * C;
+// The FFT side of a transform: image N zero-padded onto grid K (or cropped
+// back), per-axis scale tables (S, S^H), radix schedules, twiddles, coils and
+// the two pass buffers.  The plan has one (N -> K with the deapodization);
+// a Toeplitz operator has its own (N -> 2N, no scaling).
+struct FftGeom {
+    int d = 1;
+    int64_t N[kMaxDim] = {1, 1, 1};
+    int64_t K[kMaxDim] = {1, 1, 1};
+    const RadixPlan *rp = nullptr;  // [d]
+    float2 *const *tw = nullptr;    // [d]
+    float *const *scale = nullptr;  // [d]
+    const float2 *coils = nullptr;  // [C][N^d] in coil mode, else nullptr
+    int C = 1;
+    float2 *grid = nullptr;
+    float2 *tmp = nullptr;
+    int fft_groups = 1024;
+};
+
+FftGeom plan_fft(const nufft_plan_s *p) {
+    FftGeom f;
+    f.d = p->d;
+    for (int a = 0; a < p->d; ++a) {
+        f.N[a] = p->N[a];
+        f.K[a] = p->K[a];
+    }
+    f.rp = p->rp;
+    f.tw = p->tw;
+    f.scale = p->scale;
+    f.coils = p->coil_mode ? p->coils : nullptr;
+    f.C = p->coil_mode ? p->C : 1;
+    f.grid = p->grid;
+    f.tmp = p->tmp;
+    f.fft_groups = p->fft_groups;
+    return f;
+}
+
+// out = F S x: x [B][N^d] -> out [B*C][K^d] (times the coils in coil mode).
+// With mult (Toeplitz product) the last forward pass's output is multiplied
+// by it; only d = 1 does this here, d >= 2 fuses it into run_shfh.
+int run_fs(nufft_plan_s *p, const FftGeom &f, const float2 *x, int B, float2 *out, hipStream_t s,
+           const float2 *mult = nullptr) {
+    const int d = f.d;
+    const int64_t grids = int64_t(B) * f.C;
     const float2 *cur = x;
     for (int pass = 0; pass < d; ++pass) {
         const int ax = d - 1 - pass;
-        float2 *dst = (pass == d - 1) ? out : (((d - 1 - pass) % 2 == 0) ? p->grid : p->tmp);
+        float2 *dst = (pass == d - 1) ? out : (((d - 1 - pass) % 2 == 0) ? f.grid : f.tmp);
         if (pass == 0) {
             FirstPassArgs a{};
             a.x = cur;
             a.out = dst;
-            a.tw = p->tw[ax];
-            a.rp = p->rp[ax];
-            a.coils = p->coil_mode ? p->coils : nullptr;
-            a.C = C;
+            a.tw = f.tw[ax];
+            a.rp = f.rp[ax];
+            a.coils = f.coils;
+            a.C = f.C;
             a.B = B;
-            a.K = int(p->K[ax]);
-            a.N = int(p->N[ax]);
+            a.K = int(f.K[ax]);
+            a.N = int(f.N[ax]);
             a.rows = 1;
-            for (int b = 0; b < d - 1; ++b) a.rows *= p->N[b];
+            for (int b = 0; b < d - 1; ++b) a.rows *= f.N[b];
             a.d = d;
-            a.target_groups = p->fft_groups;
+            a.target_groups = f.fft_groups;
+            a.mult = (d == 1) ? mult : nullptr;
             for (int b = 0; b < d; ++b) {
-                a.Nax[b] = int(p->N[b]);
-                a.scale[b] = p->scale[b];
+                a.Nax[b] = int(f.N[b]);
+                a.scale[b] = f.scale[b];
             }
             HIP_TRY(timed(p, kFirstPass, s, [&] { return launch_first_pass(a, s); }), "forward first FFT pass");
         } else {
             StridedPassArgs a{};
             a.in = cur;
             a.out = dst;
-            a.tw = p->tw[ax];
-            a.rp = p->rp[ax];
-            a.K = int(p->K[ax]);
-            a.Lin = int(p->N[ax]);
-            a.Lout = int(p->K[ax]);
+            a.tw = f.tw[ax];
+            a.rp = f.rp[ax];
+            a.K = int(f.K[ax]);
+            a.Lin = int(f.N[ax]);
+            a.Lout = int(f.K[ax]);
             a.outer = 1;
-            for (int b = 0; b < ax; ++b) a.outer *= p->N[b];
+            for (int b = 0; b < ax; ++b) a.outer *= f.N[b];
             a.inner = 1;
-            for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
+            for (int b = ax + 1; b < d; ++b) a.inner *= f.K[b];
             a.grids = grids;
             a.inverse = false;
-            a.target_groups = p->fft_groups;
+            a.target_groups = f.fft_groups;
             HIP_TRY(timed(p, kStridedFwd, s, [&] { return launch_strided_pass(a, s); }), "forward strided FFT pass");
         }
         cur = dst;
@@ -480,50 +521,52 @@ int run_fs(nufft_plan_s *p, const float2 *x, int B, float2 *out, hipStream_t s) 
 
 // x = S^H F^H h (coil-combined): h [B*C][K^d] -> x [B][N^d].  With
 // fused_partials, h's split tiles are still partial tiles (run_vh with
-// reduce = false) and the first pass sums them.
-int run_shfh(nufft_plan_s *p, const float2 *h, int B, float2 *x, hipStream_t s, bool fused_partials = false) {
-    const int d = p->d;
-    const int C = p->coil_mode ? p->C : 1;
-    const int64_t grids = int64_t(B) * C;
+// reduce = false) and the first pass sums them.  With mult (Toeplitz
+// product, d >= 2) the first pass multiplies its input by it.
+int run_shfh(nufft_plan_s *p, const FftGeom &f, const float2 *h, int B, float2 *x, hipStream_t s,
+             bool fused_partials = false, const float2 *mult = nullptr) {
+    const int d = f.d;
+    const int64_t grids = int64_t(B) * f.C;
     const float2 *cur = h;
     for (int ax = 0; ax < d; ++ax) {
         if (ax == d - 1) {
             LastPassArgs a{};
             a.in = cur;
             a.x = x;
-            a.tw = p->tw[ax];
-            a.rp = p->rp[ax];
-            a.coils = p->coil_mode ? p->coils : nullptr;
-            a.C = C;
+            a.tw = f.tw[ax];
+            a.rp = f.rp[ax];
+            a.coils = f.coils;
+            a.C = f.C;
             a.B = B;
-            a.K = int(p->K[ax]);
-            a.N = int(p->N[ax]);
+            a.K = int(f.K[ax]);
+            a.N = int(f.N[ax]);
             a.rows = 1;
-            for (int b = 0; b < d - 1; ++b) a.rows *= p->N[b];
+            for (int b = 0; b < d - 1; ++b) a.rows *= f.N[b];
             a.d = d;
-            a.target_groups = p->fft_groups;
+            a.target_groups = f.fft_groups;
             for (int b = 0; b < d; ++b) {
-                a.Nax[b] = int(p->N[b]);
-                a.scale[b] = p->scale[b];
+                a.Nax[b] = int(f.N[b]);
+                a.scale[b] = f.scale[b];
             }
             HIP_TRY(timed(p, kLastPass, s, [&] { return launch_last_pass(a, s); }), "adjoint last FFT pass");
         } else {
-            float2 *dst = (ax % 2 == 0) ? p->tmp : p->grid;
+            float2 *dst = (ax % 2 == 0) ? f.tmp : f.grid;
             StridedPassArgs a{};
             a.in = cur;
             a.out = dst;
-            a.tw = p->tw[ax];
-            a.rp = p->rp[ax];
-            a.K = int(p->K[ax]);
-            a.Lin = int(p->K[ax]);
-            a.Lout = int(p->N[ax]);
+            a.tw = f.tw[ax];
+            a.rp = f.rp[ax];
+            a.K = int(f.K[ax]);
+            a.Lin = int(f.K[ax]);
+            a.Lout = int(f.N[ax]);
             a.outer = 1;
-            for (int b = 0; b < ax; ++b) a.outer *= p->N[b];
+            for (int b = 0; b < ax; ++b) a.outer *= f.N[b];
             a.inner = 1;
-            for (int b = ax + 1; b < d; ++b) a.inner *= p->K[b];
+            for (int b = ax + 1; b < d; ++b) a.inner *= f.K[b];
             a.grids = grids;
             a.inverse = true;
-            a.target_groups = p->fft_groups;
+            a.target_groups = f.fft_groups;
+            if (ax == 0) a.mult = mult;
             if (ax == 0 && fused_partials && p->n_hot > 0) {
                 a.hot_of_tile = p->hot_of_tile;
                 a.hot = p->hot;
@@ -746,6 +789,84 @@ int multi_run(nufft_multi_s *m, bool forward, const void *const *in, void *const
     }
     HIP_TRY(hipGraphLaunch(gc.exec, user), "launch the multi-problem graph");
     return NUFFT_OK;
+}
+
+}  // namespace
+
+constexpr uint64_t kToeplitzMagic = 0x4e5546544f45504cull;  // "NUFTOEPL"
+
+struct nufft_toeplitz_s {
+    uint64_t magic = kToeplitzMagic;
+    nufft_plan_t plan = nullptr;
+    int d = 1;
+    int64_t N[kMaxDim] = {1, 1, 1};
+    int64_t P[kMaxDim] = {1, 1, 1};  // 2N
+    int64_t elems = 1;               // prod(2N)
+    RadixPlan rp[kMaxDim];
+    float2 *tw[kMaxDim] = {nullptr, nullptr, nullptr};
+    float *ones[kMaxDim] = {nullptr, nullptr, nullptr};
+    float *inv[kMaxDim] = {nullptr, nullptr, nullptr};  // 1 / (2 N_a)
+    float2 *phat = nullptr;   // [prod(2N)]
+    int cap = 0;              // grids the workspace holds
+    float2 *grid = nullptr;   // pass buffers, [cap][prod(2N)] each
+    float2 *tmp = nullptr;
+    float2 *grid2 = nullptr;  // the spectrum between the forward and inverse passes
+};
+
+namespace {
+
+std::set<const void *> g_toeplitz_registry;
+
+int check_toeplitz(nufft_toeplitz_t t) {
+    if (!t) return fail(NUFFT_ERR_BAD_PLAN, "Toeplitz handle is NULL");
+    std::lock_guard<std::mutex> lk(g_registry_mu);
+    if (!g_toeplitz_registry.count(t) || t->magic != kToeplitzMagic)
+        return fail(NUFFT_ERR_BAD_PLAN, "Toeplitz handle is not live");
+    return NUFFT_OK;
+}
+
+void destroy_toeplitz(nufft_toeplitz_s *t) {
+    for (int a = 0; a < kMaxDim; ++a) {
+        dfree(t->tw[a]);
+        dfree(t->ones[a]);
+        dfree(t->inv[a]);
+    }
+    dfree(t->phat);
+    dfree(t->grid);
+    dfree(t->tmp);
+    dfree(t->grid2);
+}
+
+int ensure_toeplitz_workspace(nufft_toeplitz_s *t, int grids) {
+    if (grids <= t->cap) return NUFFT_OK;
+    dfree(t->grid);
+    dfree(t->tmp);
+    dfree(t->grid2);
+    t->cap = 0;
+    const size_t n = size_t(grids) * size_t(t->elems);
+    HIP_TRY(dmalloc(&t->grid, n), "allocate Toeplitz workspace");
+    HIP_TRY(dmalloc(&t->tmp, n), "allocate Toeplitz workspace");
+    HIP_TRY(dmalloc(&t->grid2, n), "allocate Toeplitz workspace");
+    t->cap = grids;
+    return NUFFT_OK;
+}
+
+// psf = true: image = grid = 2N, scale 1/(2N_a) (the point-spread function's
+// transform); false: image N on grid 2N, no scaling (the application).
+FftGeom toeplitz_fft(const nufft_toeplitz_s *t, bool psf) {
+    FftGeom f;
+    f.d = t->d;
+    for (int a = 0; a < t->d; ++a) {
+        f.N[a] = psf ? t->P[a] : t->N[a];
+        f.K[a] = t->P[a];
+    }
+    f.rp = t->rp;
+    f.tw = t->tw;
+    f.scale = psf ? t->inv : t->ones;
+    f.grid = t->grid;
+    f.tmp = t->tmp;
+    f.fft_groups = t->plan->fft_groups;
+    return f;
 }
 
 }  // namespace
@@ -1101,7 +1222,7 @@ int nufft_forward_batched(nufft_plan_t plan, int B, const void *x_dev, void *y_d
     const int C = plan->coil_mode ? plan->C : 1;
     if ((st = ensure_workspace(plan, B * C))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = run_fs(plan, static_cast<const float2 *>(x_dev), B, plan->grid, s))) return st;
+    if ((st = run_fs(plan, plan_fft(plan), static_cast<const float2 *>(x_dev), B, plan->grid, s))) return st;
     return run_v(plan, plan->grid, B * C, static_cast<float2 *>(y_dev), s);
 }
 
@@ -1115,7 +1236,7 @@ int nufft_adjoint_batched(nufft_plan_t plan, int B, const void *y_dev, void *x_d
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool fuse = plan->fuse_reduce;
     if ((st = run_vh(plan, static_cast<const float2 *>(y_dev), B * C, plan->grid, s, !fuse))) return st;
-    return run_shfh(plan, plan->grid, B, static_cast<float2 *>(x_dev), s, fuse);
+    return run_shfh(plan, plan_fft(plan), plan->grid, B, static_cast<float2 *>(x_dev), s, fuse);
 }
 
 int nufft_forward(nufft_plan_t plan, const void *x_dev, void *y_dev, void *stream) {
@@ -1133,7 +1254,7 @@ int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev, 
     const int C = plan->coil_mode ? plan->C : 1;
     if ((st = ensure_workspace(plan, C))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = run_fs(plan, static_cast<const float2 *>(x_dev), 1, plan->grid, s))) return st;
+    if ((st = run_fs(plan, plan_fft(plan), static_cast<const float2 *>(x_dev), 1, plan->grid, s))) return st;
     GradArgs a{};
     a.geo = plan->geom();
     a.om_sorted = plan->om_sorted;
@@ -1153,7 +1274,7 @@ int nufft_stage_fs(nufft_plan_t plan, const void *x_dev, void *G_dev, void *stre
     if (st) return st;
     if (!x_dev || !G_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
     if (plan->coil_mode) return fail(NUFFT_ERR_UNSUPPORTED, "stage calls take no coils");
-    return run_fs(plan, static_cast<const float2 *>(x_dev), 1, static_cast<float2 *>(G_dev),
+    return run_fs(plan, plan_fft(plan), static_cast<const float2 *>(x_dev), 1, static_cast<float2 *>(G_dev),
                   static_cast<hipStream_t>(stream));
 }
 
@@ -1178,7 +1299,7 @@ int nufft_stage_shfh(nufft_plan_t plan, const void *h_dev, void *x_dev, void *st
     if (st) return st;
     if (!h_dev || !x_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
     if (plan->coil_mode) return fail(NUFFT_ERR_UNSUPPORTED, "stage calls take no coils");
-    return run_shfh(plan, static_cast<const float2 *>(h_dev), 1, static_cast<float2 *>(x_dev),
+    return run_shfh(plan, plan_fft(plan), static_cast<const float2 *>(h_dev), 1, static_cast<float2 *>(x_dev),
                     static_cast<hipStream_t>(stream));
 }
 
@@ -1249,4 +1370,136 @@ int nufft_destroy(nufft_plan_t plan) {
     return NUFFT_OK;
 }
 
+
+// ------------------------------------------------------------ Toeplitz normal operator
+// A^H W A x = crop( F^-1( P * F( pad(x) ) ) ) on the 2N grid, P the FFT of the
+// point-spread function p[Delta] = sum_m w_m e^{+i omega_m . Delta},
+// Delta in [-N, N)^d, divided by prod(2N): no interpolation per application.
+int nufft_toeplitz_plan(nufft_plan_t plan, const float *w_dev, void *stream, nufft_toeplitz_t *out) {
+    if (!out) return fail(NUFFT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int d = plan->d;
+    int64_t N2[kMaxDim] = {1, 1, 1}, K2[kMaxDim] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) {
+        N2[a] = 2 * plan->N[a];
+        K2[a] = 2 * plan->K[a];
+        if (N2[a] > 4096 || !smooth235(N2[a]))
+            return fail(NUFFT_ERR_UNSUPPORTED, "Toeplitz grid 2N[%d]=%lld must be 2-3-5 smooth and <= 4096", a,
+                        (long long)N2[a]);
+    }
+    auto t = std::make_unique<nufft_toeplitz_s>();
+    t->plan = plan;
+    t->d = d;
+    t->elems = 1;
+    for (int a = 0; a < d; ++a) {
+        t->N[a] = plan->N[a];
+        t->P[a] = N2[a];
+        t->elems *= N2[a];
+        if (!radix_plan(int(N2[a]), &t->rp[a])) return fail(NUFFT_ERR_UNSUPPORTED, "no radix plan for 2N");
+        std::vector<float> ones(size_t(plan->N[a]), 1.0f);
+        std::vector<float> inv(size_t(N2[a]), float(1.0 / double(N2[a])));
+        hipError_t e;
+        if ((e = upload(&t->tw[a], twiddles(int(N2[a])))) != hipSuccess ||
+            (e = upload(&t->ones[a], ones)) != hipSuccess || (e = upload(&t->inv[a], inv)) != hipSuccess) {
+            destroy_toeplitz(t.get());
+            return hip_fail(e, "upload Toeplitz constants");
+        }
+    }
+    // sample weights as complex values (1 when w_dev is NULL)
+    const int64_t M = plan->M;
+    std::vector<float2> wc(size_t(std::max<int64_t>(M, 1)), make_float2(1.0f, 0.0f));
+    if (w_dev && M > 0) {
+        std::vector<float> wh(static_cast<size_t>(M));
+        hipError_t e = hipMemcpyAsync(wh.data(), w_dev, size_t(M) * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            destroy_toeplitz(t.get());
+            return hip_fail(e, "read sample weights");
+        }
+        for (int64_t m = 0; m < M; ++m) {
+            if (!std::isfinite(wh[size_t(m)])) {
+                destroy_toeplitz(t.get());
+                return fail(NUFFT_ERR_NONFINITE, "weight %lld is not finite", (long long)m);
+            }
+            wc[size_t(m)] = make_float2(wh[size_t(m)], 0.0f);
+        }
+    }
+    float2 *wdev = nullptr, *psf = nullptr;
+    nufft_plan_t pp = nullptr;
+    hipError_t e;
+    if ((e = upload(&wdev, wc)) != hipSuccess || (e = dmalloc(&psf, size_t(t->elems))) != hipSuccess ||
+        (e = dmalloc(&t->phat, size_t(t->elems))) != hipSuccess) {
+        dfree(wdev);
+        dfree(psf);
+        destroy_toeplitz(t.get());
+        return hip_fail(e, "allocate Toeplitz buffers");
+    }
+    // p = adjoint NUFFT of the weights with image 2N on grid 2K (same J)
+    st = nufft_plan_ex(d, N2, K2, plan->J, M, plan->om, nullptr, stream, &pp);
+    if (!st) st = nufft_adjoint(pp, wdev, psf, stream);
+    if (!st) st = ensure_toeplitz_workspace(t.get(), 1);
+    if (!st) {
+        // P = F(p placed at Delta mod 2N) / prod(2N): the forward passes with
+        // image = grid = 2N place the centred p circularly; the scale tables
+        // carry 1 / (2N_a)
+        FftGeom f = toeplitz_fft(t.get(), true);
+        f.coils = nullptr;
+        f.C = 1;
+        st = run_fs(plan, f, psf, 1, t->phat, s);
+    }
+    if (!st) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "Toeplitz point-spread function");
+    }
+    if (pp) (void)nufft_destroy(pp);
+    dfree(wdev);
+    dfree(psf);
+    if (st) {
+        destroy_toeplitz(t.get());
+        return st;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_registry_mu);
+        g_toeplitz_registry.insert(t.get());
+    }
+    *out = t.release();
+    return NUFFT_OK;
+}
+
+int nufft_toeplitz_apply(nufft_toeplitz_t t, int B, const void *x_dev, void *out_dev, void *stream) {
+    int st = check_toeplitz(t);
+    if (st) return st;
+    nufft_plan_t plan = t->plan;
+    if ((st = begin_call(plan, stream))) return fail(NUFFT_ERR_BAD_PLAN, "the operator's plan is gone");
+    if (B < 1) return fail(NUFFT_ERR_INVALID_ARG, "B must be >= 1");
+    if (!x_dev || !out_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    const int C = plan->coil_mode ? plan->C : 1;
+    if ((st = ensure_toeplitz_workspace(t, B * C))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FftGeom f = toeplitz_fft(t, false);
+    f.coils = plan->coil_mode ? plan->coils : nullptr;
+    f.C = C;
+    // forward passes into the grid buffer (the product for d = 1 happens
+    // there), inverse passes with the product fused into the first
+    float2 *G = t->grid2;
+    if ((st = run_fs(plan, f, static_cast<const float2 *>(x_dev), B, G, s, t->phat))) return st;
+    return run_shfh(plan, f, G, B, static_cast<float2 *>(out_dev), s, false, t->d >= 2 ? t->phat : nullptr);
+}
+
+int nufft_toeplitz_destroy(nufft_toeplitz_t t) {
+    int st = check_toeplitz(t);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_registry_mu);
+        g_toeplitz_registry.erase(t);
+    }
+    (void)hipDeviceSynchronize();
+    destroy_toeplitz(t);
+    t->magic = 0;
+    delete t;
+    return NUFFT_OK;
+}
 }  // extern "C"

@@ -268,7 +268,15 @@ __global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lin
     __syncthreads();
     lds_fft<THREADS, false, false>(s, nl, K, K, 1, a.rp, tw);
     float2 *out = a.out + l0 * K;
-    for (int e = threadIdx.x; e < nl * K; e += THREADS) out[e] = s[e];
+    if (a.mult) {
+        for (int e = threadIdx.x; e < nl * K; e += THREADS) {
+            const int lw = e / K, q = e - lw * K;
+            const int64_t r = (l0 + lw) % a.rows;
+            out[e] = cmul(s[e], a.mult[r * K + q]);
+        }
+    } else {
+        for (int e = threadIdx.x; e < nl * K; e += THREADS) out[e] = s[e];
+    }
 }
 
 template <int THREADS, bool INV>
@@ -291,7 +299,9 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
         const int q = e / W, w = e - q * W;
         float2 v = make_float2(0.f, 0.f);
         if (w < wv) {
-            const int i = (a.Lin == K) ? q : src_row(q, a.Lin, K);
+            // forward: grid row q takes image row src_row (zero rows when Lin < K,
+            // the centring shift when Lin == K); inverse: the input is the grid
+            const int i = INV ? q : src_row(q, a.Lin, K);
             if (i >= 0) {
                 int hot = -1;
                 int cell = 0;
@@ -313,6 +323,7 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
                 }
                 if (hot < 0) {
                     v = in[int64_t(i) * a.inner + w];
+                    if (a.mult) v = cmul(v, a.mult[(o * a.Lin + i) * a.inner + c0 + w]);
                 } else {
                     const HotTile ht = a.hot[hot];
                     const float2 *pp = a.partials + (g * a.n_slots + ht.slot) * a.tile_cells + cell;
@@ -327,7 +338,7 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
     for (int e = threadIdx.x; e < a.Lout * W; e += THREADS) {
         const int i = e / W, w = e - i * W;
         if (w < wv) {
-            const int q = (a.Lout == K) ? i : pad_pos(i, a.Lout, K);
+            const int q = INV ? pad_pos(i, a.Lout, K) : i;
             out[int64_t(i) * a.inner + w] = s[q * W + w];
         }
     }

@@ -81,6 +81,7 @@ struct FirstPassArgs {
     int d;
     int Nax[kMaxDim];
     const float *scale[kMaxDim];
+    const float2 *mult;  // d = 1 Toeplitz product: the output line times mult[q] (nullptr: none)
     int target_groups;  // workgroups the launch aims for
 };
 hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s);
@@ -97,6 +98,7 @@ struct StridedPassArgs {
     int64_t outer, inner;
     int64_t grids;
     bool inverse;
+    const float2 *mult;  // inverse pass: the input times mult (same layout, shared by all grids)
     int target_groups;
     // First inverse pass of the adjoint only (hot_of_tile != nullptr): cells of
     // split gridding tiles are read as the sum of their partial tiles.

@@ -207,6 +207,10 @@ class Plan:
             _lib.call("nufft_grad_points", self.handle, _ptr(x), _ptr(gy), _ptr(g), _stream(self.device))
         return g
 
+    def toeplitz(self, weights: torch.Tensor | None = None) -> "Toeplitz":
+        """The normal operator A^H W A of this plan as a Toeplitz embedding."""
+        return Toeplitz(self, weights)
+
     # ------------------------------------------------------------ stages
     def stage_fs(self, x: torch.Tensor) -> torch.Tensor:
         _need(x, torch.complex64, self.N, "x", self.device)
@@ -235,6 +239,57 @@ class Plan:
         with torch.cuda.device(self.device):
             _lib.call("nufft_stage_shfh", self.handle, _ptr(h), _ptr(x), _stream(self.device))
         return x
+
+
+class Toeplitz:
+    """The normal operator A^H W A of a plan applied through its Toeplitz
+    embedding (include/nufft_mi355x.h, nufft_toeplitz_*): two FFTs of size 2N
+    and a product per application, no interpolation.  `weights`: float32 [M]
+    sample weights (density compensation) on the plan's device, None for 1.
+    In coil mode the plan's coils at call time are applied and combined.
+    Keep it closed before its plan."""
+
+    def __init__(self, plan: Plan, weights: torch.Tensor | None = None):
+        self.plan = plan
+        self.N = plan.N
+        self.device = plan.device
+        self._handle = ctypes.c_void_p()
+        if weights is not None:
+            _need(weights, torch.float32, (plan.M,), "weights", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_toeplitz_plan", plan.handle, _ptr(weights) if weights is not None else None,
+                      _stream(self.device), ctypes.byref(self._handle))
+
+    def close(self):
+        if self._handle:
+            _lib.call("nufft_toeplitz_destroy", self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """A^H W A x for x [N...] or a batch [B, N...]."""
+        batched = x.dim() == len(self.N) + 1
+        B = int(x.shape[0]) if batched else 1
+        shape = ((B,) if batched else ()) + self.N
+        _need(x, torch.complex64, shape, "x", self.device)
+        o = out if out is not None else torch.empty(shape, dtype=torch.complex64, device=self.device)
+        _need(o, torch.complex64, shape, "out", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_toeplitz_apply", self._handle, B, _ptr(x), _ptr(o), _stream(self.device))
+        return o
+
+    __call__ = apply
 
 
 class MultiPlan:

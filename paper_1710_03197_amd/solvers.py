@@ -17,21 +17,29 @@ def _dot_re(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
 
 
 def cg_normal(plan: Plan, y: torch.Tensor, iters: int = 30, x0: torch.Tensor | None = None,
-              history: bool = False):
+              history: bool = False, normal=None):
     """`iters` CG iterations on A^H A x = A^H y, x0 = 0 by default, no
-    preconditioner, no restart.  Returns x (and the residual norms per
+    preconditioner, no restart.  A^H A is applied as a forward + adjoint pair,
+    or by `normal` (e.g. the plan's Toeplitz operator, called as
+    normal(p, out=...)) when given.  Returns x (and the residual norms per
     iteration when history=True; reading them synchronises once at the end)."""
     b = plan.adjoint(y)
+    ybuf = torch.empty_like(y)
+
+    def apply(v, out):
+        if normal is not None:
+            return normal(v, out=out)
+        plan.forward(v, out=ybuf)
+        return plan.adjoint(ybuf, out=out)
+
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    r = b.clone() if x0 is None else b - plan.adjoint(plan.forward(x))
+    r = b.clone() if x0 is None else b - apply(x, torch.empty_like(b))
     p = r.clone()
     rr = _dot_re(r, r)
     hist = [rr.sqrt()]
-    ybuf = torch.empty_like(y)
     ap = torch.empty_like(b)
     for _ in range(iters):
-        plan.forward(p, out=ybuf)
-        plan.adjoint(ybuf, out=ap)
+        apply(p, ap)
         pap = _dot_re(p, ap)
         alpha = rr / pap
         x.add_(p * alpha)
