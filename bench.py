@@ -126,6 +126,39 @@ def time_graph_pairs(plan, x, y, xa, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def time_toeplitz(plan, x, xa, steps, warmup, sec_pair):
+    """The Toeplitz normal operator A^H A of the same plan (two 2N-grid FFTs
+    and a product per application) against the pair A^H (A x): time per
+    application, and its difference to the pair (both approximate A^H A; the
+    oracle parity of the operator is in the tests)."""
+    import time
+    import torch
+    t0 = time.perf_counter()
+    T = plan.toeplitz()
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    out = torch.empty_like(xa)
+    y = plan.forward(x)
+    ref = plan.adjoint(y)
+    T(x, out=out)
+    torch.cuda.synchronize()
+    diff = float(torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref))
+    for _ in range(warmup):
+        T(x, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        T(x, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / steps
+    T.close()
+    return {"applications_per_s": round(1.0 / sec, 2), "ms_per_application": round(sec * 1e3, 4),
+            "speedup_vs_pair": round(sec_pair / sec, 3), "rel_diff_vs_pair": diff,
+            "plan_ms": round(plan_ms, 2)}
+
+
 def kernel_times(plan, x, y, xa, steps):
     """Per-kernel launches and mean duration (ms) over `steps` pairs, from the
     library's HIP events on the launch stream."""
@@ -201,11 +234,12 @@ def bench_2d(dev, steps, warmup, orc_mod, tune="cache", no_graph=False):
     sec = time_pairs(plan, x, y, xa, steps, warmup)
     ktimes = kernel_times(plan, x, y, xa, steps)
     sec_graph = None if no_graph else time_graph_pairs(plan, x, y, xa, steps, warmup)
+    toep = time_toeplitz(plan, x, xa, steps, warmup, sec)
     alg = algorithmic_bytes(N, K, M, J)
     info = plan.info()
     plan.close()
     return dict(sec=sec, sec_graph=sec_graph, ktimes=ktimes, alg=alg, err_f=err_f, err_a=err_a, N=N, K=K, M=M,
-                J=J, info=info, tuned=tuned)
+                J=J, info=info, tuned=tuned, toeplitz=toep)
 
 
 def bench_3d(dev, steps, warmup, orc_mod, tune="cache"):
@@ -227,9 +261,10 @@ def bench_3d(dev, steps, warmup, orc_mod, tune="cache"):
         raise SystemExit(f"3D parity gate failed: forward {err_f:.2e}")
     sec = time_pairs(plan, x, y, xa, steps, warmup)
     ktimes = kernel_times(plan, x, y, xa, max(2, steps // 2))
+    toep = time_toeplitz(plan, x, xa, steps, warmup, sec)
     alg = algorithmic_bytes(N, K, M, J)
     plan.close()
-    return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f, tuned=tuned)
+    return dict(sec=sec, ktimes=ktimes, alg=alg, err_f=err_f, tuned=tuned, toeplitz=toep)
 
 
 def bench_batched(dev, steps, warmup, orc_mod, n_problems=24):
@@ -352,6 +387,7 @@ def main():
         "pair_bytes_model": int(sum(r2["alg"].values())),
         "pair_model_frac": round(sum(r2["alg"].values()) / r2["sec"] / 1e9 / HBM_PEAK_GBS, 4),
         "plan": r2["info"], "kernels_sha": khash, "tuning": r2["tuned"],
+        "toeplitz_normal_2d": r2["toeplitz"],
     }
     if not args.no_3d:
         r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod, tune=args.tune)
@@ -364,6 +400,7 @@ def main():
             "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r3["ktimes"].items()},
             "roofline": roof3,
             "tuning": r3["tuned"],
+            "toeplitz_normal": r3["toeplitz"],
         }
     if not args.no_batched:
         extra["batched_vs_looped"] = bench_batched(dev, max(3, args.steps // 40), 2, orc_mod)
