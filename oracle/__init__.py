@@ -339,6 +339,21 @@ def toeplitz_normal(x, om, N, K, J, w=None, fft: bool = False) -> np.ndarray:
     return (toeplitz_conv_fft if fft else toeplitz_conv)(p, x, N)
 
 
+# ------------------------------------------------------------------ density compensation
+def density_compensation(om, N, K, J, iters: int, w0=None) -> np.ndarray:
+    """Sampling-density weights by the stable iterations of the paper's
+    Section 2.2 ("Density compensation and gridding", after Pipe and Menon):
+    w <- w / |A A^H w| elementwise, from w0 (ones by default), with the oracle
+    pair.  (The paper divides by A A^H w; with the image range [-N/2, N/2)
+    that is complex and its modulus is taken.)"""
+    M = np.asarray(om).shape[0]
+    w = np.ones(M) if w0 is None else np.asarray(w0, np.float64).copy()
+    for _ in range(iters):
+        u = np.abs(forward(adjoint(w.astype(np.complex128), om, N, K, J), om, N, K, J))
+        w = np.where(u > 0, w / np.where(u > 0, u, 1.0), w)
+    return w
+
+
 # ------------------------------------------------------------------ CG
 def cg(apply_normal, b, iters: int):
     """Conjugate gradient on the Hermitian positive semi-definite system
