@@ -253,6 +253,22 @@ int nufft_toeplitz_plan(nufft_plan_t plan, const float *w_dev, void *stream, nuf
 int nufft_toeplitz_apply(nufft_toeplitz_t t, int B, const void *x_dev, void *out_dev, void *stream);
 int nufft_toeplitz_destroy(nufft_toeplitz_t t);
 
+/* Sampling-density compensation weights (Section 2.2, "Density compensation
+ * and gridding", Eq. of the stable iterations, after Pipe and Menon):
+ *   w <- w / (V V^H w)   (elementwise), `iters` times,
+ * with V the plan's interpolator (the gather of Eq. A = VFS) with the
+ * Kaiser-Bessel kernel normalised to peak 1, and V^H its gridding.  The paper
+ * writes A A^H; Pipe and Menon's iteration divides by the gridding kernel's
+ * convolution at the samples, which V V^H is: real and positive for
+ * positive w, so the iteration stays real and stable (with the whole A the
+ * quotient is complex and oscillates on undersampled radial trajectories).
+ * A zero or non-finite (V V^H w)_m leaves w_m unchanged.  Coils
+ * are ignored (the weights belong to the trajectory).  w_dev: device float
+ * [M] in the caller's sample order, the starting weights on entry (e.g. all
+ * 1) and the result on return.  The gridding reconstruction is then
+ * x = A^H (y . w).  Allocates temporary buffers; synchronous on `stream`. */
+int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void *stream);
+
 /* Synchronise the plan's last stream and free everything.  A NULL, destroyed
  * or foreign handle returns BAD_PLAN and is not touched. */
 int nufft_destroy(nufft_plan_t plan);

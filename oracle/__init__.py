@@ -343,13 +343,17 @@ def toeplitz_normal(x, om, N, K, J, w=None, fft: bool = False) -> np.ndarray:
 def density_compensation(om, N, K, J, iters: int, w0=None) -> np.ndarray:
     """Sampling-density weights by the stable iterations of the paper's
     Section 2.2 ("Density compensation and gridding", after Pipe and Menon):
-    w <- w / |A A^H w| elementwise, from w0 (ones by default), with the oracle
-    pair.  (The paper divides by A A^H w; with the image range [-N/2, N/2)
-    that is complex and its modulus is taken.)"""
+    w <- w / (V V^H w) elementwise, from w0 (ones by default), V the oracle
+    interpolator and V^H its gridding with the kernel normalised to peak 1
+    (the paper writes A A^H; Pipe and Menon divide by the gridding kernel's
+    convolution at the samples, which V V^H is)."""
     M = np.asarray(om).shape[0]
+    c2 = 1.0
+    for n, k in zip(N, K):
+        c2 *= i0(kb_beta(J, k / n)) ** 2
     w = np.ones(M) if w0 is None else np.asarray(w0, np.float64).copy()
     for _ in range(iters):
-        u = np.abs(forward(adjoint(w.astype(np.complex128), om, N, K, J), om, N, K, J))
+        u = np.abs(interp(grid(w.astype(np.complex128), om, N, K, J), om, N, K, J)) / c2
         w = np.where(u > 0, w / np.where(u > 0, u, 1.0), w)
     return w
 

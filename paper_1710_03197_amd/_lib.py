@@ -83,6 +83,7 @@ _SIGS = {
     "nufft_toeplitz_plan": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
     "nufft_toeplitz_apply": [_vp, ctypes.c_int, _vp, _vp, _vp],
     "nufft_toeplitz_destroy": [_vp],
+    "nufft_density_compensation": [_vp, ctypes.c_int, _vp, _vp],
     "nufft_timing_kernels": [],
     "nufft_timing_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _i64p, _dp],
 }

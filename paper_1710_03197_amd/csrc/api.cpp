@@ -1084,7 +1084,9 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         p->seg_len = ls;
         p->segs = (L + ls - 1) / ls;
         const int lanes = rows * p->segs;
-        p->group_lanes = 64 * ((lanes + 63) / 64);
+        // a group size that divides the 256-thread workgroup (192 would leave
+        // 64 threads without a staging area)
+        p->group_lanes = lanes <= 64 ? 64 : lanes <= 128 ? 128 : 256;
         const int B = p->group_lanes;
         const int Lp = p->segs * ls;
         const int staged = B * Lp + 2 * (B + 1) + (d - 1) * (B + 1) + (d - 1) * J * (B + 1);
@@ -1501,5 +1503,40 @@ int nufft_toeplitz_destroy(nufft_toeplitz_t t) {
     t->magic = 0;
     delete t;
     return NUFFT_OK;
+}
+
+// ------------------------------------------------------------ density compensation
+int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void *stream) {
+    int st = begin_call(plan, stream);
+    if (st) return st;
+    if (iters < 0) return fail(NUFFT_ERR_INVALID_ARG, "iters must be >= 0");
+    if (plan->M > 0 && !w_dev) return fail(NUFFT_ERR_INVALID_ARG, "w is NULL");
+    if (plan->M == 0 || iters == 0) return NUFFT_OK;
+    if ((st = ensure_workspace(plan, 1))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float2 *wc = nullptr, *u = nullptr;
+    hipError_t e;
+    if ((e = dmalloc(&wc, size_t(plan->M))) != hipSuccess || (e = dmalloc(&u, size_t(plan->M))) != hipSuccess) {
+        dfree(wc);
+        dfree(u);
+        return hip_fail(e, "allocate density-compensation buffers");
+    }
+    // u = V V^H w with the kernel normalised to peak 1: gridding of w / c onto
+    // the oversampled grid, interpolation, and a division by c again
+    double c = 1.0;
+    for (int a = 0; a < plan->d; ++a) c *= kb_i0(plan->ker[a].beta);
+    const float inv_c = float(1.0 / c);
+    st = NUFFT_OK;
+    if ((e = launch_real_to_complex(w_dev, wc, plan->M, inv_c, s)) != hipSuccess)
+        st = hip_fail(e, "weights to samples");
+    for (int it = 0; it < iters && !st; ++it) {
+        if ((st = run_vh(plan, wc, 1, plan->grid, s, true))) break;
+        if ((st = run_v(plan, plan->grid, 1, u, s))) break;
+        if ((e = launch_dc_update(w_dev, u, wc, plan->M, inv_c, s)) != hipSuccess) st = hip_fail(e, "density update");
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess && !st) st = hip_fail(e, "density compensation");
+    dfree(wc);
+    dfree(u);
+    return st;
 }
 }  // extern "C"

@@ -1219,6 +1219,29 @@ __global__ void k_permute_points(const float *om, const int *perm, int64_t M, in
     for (int ax = 0; ax < d; ++ax) out[i * d + ax] = om[m * d + ax];
 }
 
+// ------------------------------------------------------------ density compensation
+// One fixed-point step of the sampling-density weights (Pipe-Menon) with the
+// kernel normalised to peak 1: the gridding ran on wc = w * inv_c and
+// u = V V^H wc with the unnormalised kernel (peak c = prod_a I0(beta_a)), so
+// |u| * inv_c is the normalised V V^H w;  w[m] <- w[m] / (|u[m]| * inv_c)
+// (a zero or non-finite quotient keeps w[m]), and wc is refreshed for the
+// next gridding.  The 1/c pre-scaling keeps the grid values near the
+// weights' own scale (c^2d overflows float32 for d = 3 and J >= 8).
+__global__ __launch_bounds__(256) void k_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, float inv_c) {
+    const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const float a = hypotf(u[m].x, u[m].y) * inv_c;
+    float v = w[m];
+    if (a > 0.f && isfinite(a)) v = v / a;
+    w[m] = v;
+    wc[m] = make_float2(v * inv_c, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_real_to_complex(const float *w, float2 *wc, int64_t M, float scale) {
+    const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (m < M) wc[m] = make_float2(w[m] * scale, 0.f);
+}
+
 // ------------------------------------------------------------ template dispatch
 template <template <int, int> class Fn, int J>
 struct DimDispatch {
@@ -1477,6 +1500,18 @@ hipError_t launch_bin_keys(const BinArgs &a, hipStream_t s) {
     if (a.M == 0) return hipSuccess;
     const int64_t blocks = (a.M + 255) / 256;
     hipLaunchKernelGGL(k_bin_keys, dim3(unsigned(blocks)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, float inv_c, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dc_update, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, u, wc, M, inv_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_real_to_complex, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, wc, M, scale);
     return hipGetLastError();
 }
 

@@ -196,7 +196,7 @@ struct GridArgs {
     int tile_cells;
     int seg_len;       // LS: cells of a tile row one lane accumulates (4, 8 or 16)
     int segs;          // segments per tile row, ceil(T_last / LS)
-    int group_lanes;   // lanes per sample group: 64 * ceil(rows * segs / 64), rows = tile_cells / T_last
+    int group_lanes;   // lanes per sample group: 64, 128 or 256 >= rows * segs, rows = tile_cells / T_last
     int stage_floats;  // LDS floats per group (staged batch, or the group's register tile at the end)
     int chunk;  // samples per work item
     const GridItem *items;
@@ -333,6 +333,8 @@ struct BinArgs {
 };
 hipError_t launch_bin_keys(const BinArgs &a, hipStream_t s);
 hipError_t launch_iota(int *v, int64_t n, hipStream_t s);
+hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, float inv_c, hipStream_t s);
+hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s);
 hipError_t launch_permute_points(const float *om, const int *perm, int64_t M, int d, float *om_sorted,
                                  hipStream_t s);
 // Stable sort of (key, value) pairs with hipCUB; temp storage is allocated

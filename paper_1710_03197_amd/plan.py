@@ -207,6 +207,16 @@ class Plan:
             _lib.call("nufft_grad_points", self.handle, _ptr(x), _ptr(gy), _ptr(g), _stream(self.device))
         return g
 
+    def density_compensation(self, iters: int = 10, w0: torch.Tensor | None = None) -> torch.Tensor:
+        """Sampling-density weights w (float32 [M]) by `iters` Pipe-Menon steps
+        w <- w / (V V^H w) from w0 (all ones by default); coils ignored."""
+        w = (torch.ones(self.M, dtype=torch.float32, device=self.device) if w0 is None
+             else w0.detach().to(torch.float32).clone())
+        _need(w, torch.float32, (self.M,), "w", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_density_compensation", self.handle, int(iters), _ptr(w), _stream(self.device))
+        return w
+
     def toeplitz(self, weights: torch.Tensor | None = None) -> "Toeplitz":
         """The normal operator A^H W A of this plan as a Toeplitz embedding."""
         return Toeplitz(self, weights)

@@ -53,6 +53,9 @@ CASES = [
     ("2d_J7_odd", (32, 32), (64, 64), 7, lambda: np.random.default_rng(10).uniform(-np.pi, np.pi, (1500, 2)).astype(np.float32)),
     ("3d_ragged", (12, 10, 18), (24, 30, 36), 5, lambda: np.random.default_rng(11).uniform(-np.pi, np.pi, (3000, 3)).astype(np.float32)),
     ("2d_radix35", (192, 160), (384, 320), 6, lambda: data.golden_radial_2d(40, 384)),
+    # 12x12x12 tiles: 144 rows of 16 lanes per sample group (not a divisor of 256 lanes)
+    ("3d_J10_tile144", (12, 12, 12), (24, 24, 24), 10, lambda: data.koosh_ball_3d(64, 24)),
+    ("2d_J12", (24, 24), (48, 48), 12, lambda: data.radial_2d(24, 48)),
 ]
 
 

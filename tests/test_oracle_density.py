@@ -1,36 +1,76 @@
 """Pins of the oracle's sampling-density compensation (paper Section 2.2,
-"Density compensation and gridding": w <- w / A A^H w, after Pipe and Menon;
-modulus reading) against facts that do not come from the oracle:
+"Density compensation and gridding", after Pipe and Menon: w <- w / V V^H w)
+against facts that do not come from the oracle:
 
-- a full Cartesian set of frequencies 2 pi k / N gives A A^H = prod(N) I, so
-  the weights are 1 / prod(N) after one step and stay there;
-- one step against the brute-force NUDFT;
+- a dense interpolation matrix V built here from scipy's I0 and Beatty's
+  beta (not the oracle's kernel code): one step equals 1 / (V V^T 1);
+- a full Cartesian set of frequencies sees the same neighbourhood at every
+  sample, so the weights are uniform, with the value from the dense V;
 - scale invariance of a step (w -> c w gives the same next iterate);
+- convergence towards the fixed point V V^H w = 1;
 - on a radial trajectory the weights grow with the distance from the centre
   (the density of radial samples falls as 1/|k|).
 """
-import numpy as np
+import math
 
-from nudft import nudft_adjoint, nudft_forward, rel_l2
+import numpy as np
+import scipy.special
+
+from nudft import rel_l2
 from paper_1710_03197_amd import data
 
-APPROX_TOL = 5e-5
+
+def _dense_V(om, K, J):
+    """V[m, k] = prod_a phi(u_ma - k_a) over the J taps k_a = k0 + j (mod K),
+    phi(t) = I0(beta sqrt(1 - (2t/J)^2)) / I0(beta) (peak 1),
+    beta = pi sqrt((J/s)^2 (s-1/2)^2 - 0.8)
+    with s = 2; k0 = floor(u - J/2) + 1, u = omega K / (2 pi)."""
+    om = np.asarray(om, np.float64)
+    M, d = om.shape
+    beta = math.pi * math.sqrt((J / 2.0) ** 2 * 1.5 ** 2 - 0.8)
+    V = np.zeros((M,) + tuple(K))
+    for m in range(M):
+        per_axis = []
+        for a in range(d):
+            u = om[m, a] * (K[a] / (2.0 * math.pi))
+            k0 = math.floor(u - J / 2.0) + 1
+            row = np.zeros(K[a])
+            for j in range(J):
+                t = u - (k0 + j)
+                row[(k0 + j) % K[a]] += (scipy.special.i0(beta * math.sqrt(max(0.0, 1.0 - (2.0 * t / J) ** 2)))
+                                         / scipy.special.i0(beta))
+            per_axis.append(row)
+        outer = per_axis[0]
+        for r in per_axis[1:]:
+            outer = np.multiply.outer(outer, r)
+        V[m] = outer
+    return V.reshape(M, -1)
+
+
+def test_one_step_against_dense_interpolator(orc):
+    N, K = (6, 8), (12, 16)
+    om = np.random.default_rng(4).uniform(-np.pi, np.pi, (60, 2)).astype(np.float32)
+    V = _dense_V(om, K, 6)
+    ref = 1.0 / (V @ (V.T @ np.ones(60)))
+    assert rel_l2(orc.density_compensation(om, N, K, 6, 1), ref) < 1e-12
 
 
 def test_cartesian_weights_are_uniform(orc):
-    N = (8, 8)
+    """Frequencies 2 pi (k + 1/4) / 8 put every sample half-way between grid
+    points of the 16-point grid (u = 2k + 1/2, clear of the window tie-break)
+    and the set is invariant under a shift by 2 grid cells, so every sample
+    has the same neighbourhood: uniform weights up to the float32 rounding of
+    omega (~1e-7)."""
+    N, K = (8, 8), (16, 16)
     k = np.stack(np.meshgrid(np.arange(-4, 4), np.arange(-4, 4), indexing="ij"), -1).reshape(-1, 2)
-    om = (2 * np.pi * k / 8.0).astype(np.float32)
-    for iters in (1, 3):
-        w = orc.density_compensation(om, N, (16, 16), 6, iters)
-        assert rel_l2(w, np.full(len(om), 1.0 / 64)) < APPROX_TOL
-
-
-def test_one_step_against_brute_force(orc):
-    N = (6, 8)
-    om = np.random.default_rng(4).uniform(-np.pi, np.pi, (120, 2)).astype(np.float32)
-    ref = 1.0 / np.abs(nudft_forward(nudft_adjoint(np.ones(120), om, N), om, N))
-    assert rel_l2(orc.density_compensation(om, N, (12, 16), 6, 1), ref) < APPROX_TOL
+    om = (2 * np.pi * (k + 0.25) / 8.0).astype(np.float32)
+    V = _dense_V(om, K, 6)
+    ref = 1.0 / (V @ (V.T @ np.ones(len(om))))
+    assert np.ptp(ref) <= 1e-6 * ref.mean()
+    for iters in (1, 4):
+        w = orc.density_compensation(om, N, K, 6, iters)
+        assert np.ptp(w) <= 1e-6 * w.mean()
+    assert rel_l2(orc.density_compensation(om, N, K, 6, 1), ref) < 1e-12
 
 
 def test_step_is_scale_invariant(orc):
@@ -40,6 +80,18 @@ def test_step_is_scale_invariant(orc):
     a = orc.density_compensation(om, N, K, 6, 1, w0)
     b = orc.density_compensation(om, N, K, 6, 1, 7.5 * w0)
     assert rel_l2(a, b) < 1e-12
+
+
+def test_iterations_approach_the_fixed_point(orc):
+    N, K = (24, 24), (48, 48)
+    om = data.golden_radial_2d(20, 48)
+    V = _dense_V(om, K, 6)
+    res = []
+    for iters in (1, 5, 20):
+        w = orc.density_compensation(om, N, K, 6, iters)
+        res.append(np.linalg.norm(V @ (V.T @ w) - 1.0) / math.sqrt(len(w)))
+    assert res[2] < res[1] < res[0]
+    assert res[2] < 0.1
 
 
 def test_radial_weights_grow_with_radius(orc):
