@@ -359,13 +359,14 @@ def density_compensation(om, N, K, J, iters: int, w0=None) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ CG
-def cg(apply_normal, b, iters: int):
+def cg(apply_normal, b, iters: int, x0=None):
     """Conjugate gradient on the Hermitian positive semi-definite system
-    N x = b, x0 = 0, <a, b> = sum conj(a) b, a fixed number of iterations,
-    no preconditioner, no restart.  Returns (x, residual norms per iteration)."""
+    N x = b, x0 = 0 unless given, <a, b> = sum conj(a) b, a fixed number of
+    iterations, no preconditioner, no restart.  Returns (x, residual norms
+    per iteration)."""
     b = np.asarray(b, np.complex128)
-    x = np.zeros_like(b)
-    r = b.copy()
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, np.complex128).copy()
+    r = b.copy() if x0 is None else b - apply_normal(x)
     p = r.copy()
     rr = float(np.vdot(r, r).real)
     hist = [np.sqrt(rr)]
@@ -388,3 +389,78 @@ def cg_nufft(y, om, N, K, J, iters: int = 30):
     """CG on A^H A x = A^H y with the oracle pair."""
     b = adjoint(y, om, N, K, J)
     return cg(lambda p: adjoint(forward(p, om, N, K, J), om, N, K, J), b, iters)
+
+
+# ------------------------------------------------------------------ L1TV solvers
+# Paper Section 2.2, "Iterative NUFFT": image gradient by one-sided
+# differences with wrap-around (Eq. of the image gradient), TV(x) = sum over
+# axes of |grad_a x| (Eq. TV), and the variable-splitting (split Bregman)
+# iterations of L1TV-OLS and L1TV-LAD as printed there.
+def tv_grad(x, axis: int) -> np.ndarray:
+    """grad_a x = x(..., i_a + 1, ...) - x(..., i_a, ...), periodic."""
+    return np.roll(x, -1, axis=axis) - x
+
+
+def tv_grad_t(g, axis: int) -> np.ndarray:
+    """The adjoint of tv_grad: g(..., i_a - 1, ...) - g(..., i_a, ...)."""
+    return np.roll(g, 1, axis=axis) - g
+
+
+def shrink(z, t: float) -> np.ndarray:
+    """Soft threshold of complex values: z / |z| * max(|z| - t, 0)."""
+    z = np.asarray(z, np.complex128)
+    a = np.abs(z)
+    scale = np.where(a > t, (a - t) / np.where(a > 0, a, 1.0), 0.0)
+    return z * scale
+
+
+def tv_norm(x) -> float:
+    """TV(x) = sum over axes and pixels of |grad_a x|."""
+    return float(sum(np.abs(tv_grad(x, a)).sum() for a in range(np.ndim(x))))
+
+
+def l1tv(y, om, N, K, J, mu: float, lam: float, outer: int, inner: int, cg_iters: int, lad: bool = False):
+    """L1TV-OLS (lad=False) or L1TV-LAD (lad=True) reconstruction.
+
+    K = mu A^H A + lam sum_a grad_a^T grad_a.  Inner iterations:
+      rhs = mu (A^H y^k [+ d_f - b_f]) + lam sum_a grad_a^T (d_a - b_a)
+      x = K^-1 rhs   (cg_iters CG iterations from the current x)
+      d_a = shrink(grad_a x + b_a, 1/lam);  b_a += grad_a x - d_a
+      LAD: r = A^H A x - A^H y;  d_f = shrink(r + b_f, 1/mu);  b_f += r - d_f
+    Outer iteration: A^H y^{k+1} = A^H y^k + A^H y - A^H A x.
+    (The printed d_f update adds b_y^k; it is read as b_f^k, the Bregman
+    variable of the same term.)  Returns x."""
+    N = tuple(int(n) for n in N)
+    d = len(N)
+    AH = lambda v: adjoint(v, om, N, K, J)
+    AHA = lambda v: adjoint(forward(v, om, N, K, J), om, N, K, J)
+    ahy = AH(np.asarray(y, np.complex128))
+    ahyk = ahy.copy()
+    x = np.zeros(N, np.complex128)
+    dd = [np.zeros(N, np.complex128) for _ in range(d)]
+    bb = [np.zeros(N, np.complex128) for _ in range(d)]
+    df = np.zeros(N, np.complex128)
+    bf = np.zeros(N, np.complex128)
+
+    def Kop(v):
+        out = mu * AHA(v)
+        for a in range(d):
+            out = out + lam * tv_grad_t(tv_grad(v, a), a)
+        return out
+
+    for _ in range(outer):
+        for _ in range(inner):
+            rhs = mu * (ahyk + (df - bf if lad else 0.0))
+            for a in range(d):
+                rhs = rhs + lam * tv_grad_t(dd[a] - bb[a], a)
+            x, _ = cg(Kop, rhs, cg_iters, x0=x)
+            for a in range(d):
+                z = tv_grad(x, a) + bb[a]
+                dd[a] = shrink(z, 1.0 / lam)
+                bb[a] = z - dd[a]
+            if lad:
+                z = AHA(x) - ahy + bf
+                df = shrink(z, 1.0 / mu)
+                bf = z - df
+        ahyk = ahyk + ahy - AHA(x)
+    return x
