@@ -269,6 +269,31 @@ int nufft_toeplitz_destroy(nufft_toeplitz_t t);
  * x = A^H (y . w).  Allocates temporary buffers; synchronous on `stream`. */
 int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void *stream);
 
+/* ---- L1TV split-Bregman pieces (Section 2.2, "Iterative NUFFT": the image
+ * gradient, Eq. TV, and the L1TV-OLS / L1TV-LAD iterations).  Image-domain
+ * kernels, independent of any plan; every array is device complex64 in C
+ * order, images [N^d], gradient-shaped arrays [d][N^d] (axis-major).
+ *   grad_a x = x(.., i_a + 1, ..) - x(.., i_a, ..)   (wrap-around)
+ *   grad_a^T g = g(.., i_a - 1, ..) - g(.., i_a, ..)
+ *   shrink(z, t) = z / |z| * max(|z| - t, 0)
+ * All are asynchronous on `stream`; the in/out arrays must not overlap
+ * except as stated; NUFFT_ERR_INVALID_ARG on bad sizes, NULL pointers or a
+ * negative / non-finite threshold. */
+/* For every axis a and pixel: z = grad_a x + b_a; d_a = shrink(z, t);
+ * b_a = z - d_a (d_dev, b_dev: [d][N^d], updated in place). */
+int nufft_tv_shrink(int d, const int64_t *N, const void *x_dev, void *d_dev, void *b_dev, float t, void *stream);
+/* rhs = mu (ahy + df - bf) + lam sum_a grad_a^T (d_a - b_a); df and bf
+ * (the LAD data-term split) both NULL for L1TV-OLS. */
+int nufft_tv_rhs(int d, const int64_t *N, float mu, const void *ahy_dev, const void *df_dev, const void *bf_dev,
+                 float lam, const void *d_dev, const void *b_dev, void *rhs_dev, void *stream);
+/* out = mu ahax + lam sum_a grad_a^T grad_a x, ahax = A^H A x computed by the
+ * caller (pair or Toeplitz operator): the system matrix K of the inner
+ * iterations applied to x. */
+int nufft_tv_normal(int d, const int64_t *N, float mu, const void *ahax_dev, float lam, const void *x_dev,
+                    void *out_dev, void *stream);
+/* n complex values: z = r + b; d = shrink(z, t); b = z - d (d, b in place). */
+int nufft_bregman_shrink(int64_t n, const void *r_dev, void *d_dev, void *b_dev, float t, void *stream);
+
 /* Synchronise the plan's last stream and free everything.  A NULL, destroyed
  * or foreign handle returns BAD_PLAN and is not touched. */
 int nufft_destroy(nufft_plan_t plan);

@@ -84,6 +84,10 @@ _SIGS = {
     "nufft_toeplitz_apply": [_vp, ctypes.c_int, _vp, _vp, _vp],
     "nufft_toeplitz_destroy": [_vp],
     "nufft_density_compensation": [_vp, ctypes.c_int, _vp, _vp],
+    "nufft_tv_shrink": [ctypes.c_int, _i64p, _vp, _vp, _vp, ctypes.c_float, _vp],
+    "nufft_tv_rhs": [ctypes.c_int, _i64p, ctypes.c_float, _vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _vp],
+    "nufft_tv_normal": [ctypes.c_int, _i64p, ctypes.c_float, _vp, ctypes.c_float, _vp, _vp, _vp],
+    "nufft_bregman_shrink": [ctypes.c_int64, _vp, _vp, _vp, ctypes.c_float, _vp],
     "nufft_timing_kernels": [],
     "nufft_timing_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _i64p, _dp],
 }

@@ -1539,4 +1539,62 @@ int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void 
     dfree(u);
     return st;
 }
+
+// ------------------------------------------------------------ TV split-Bregman pieces
+namespace {
+int check_image(int d, const int64_t *N) {
+    if (d < 1 || d > 3) return fail(NUFFT_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (!N) return fail(NUFFT_ERR_INVALID_ARG, "N is NULL");
+    for (int a = 0; a < d; ++a)
+        if (N[a] < 1) return fail(NUFFT_ERR_INVALID_ARG, "N[%d] must be >= 1", a);
+    return NUFFT_OK;
+}
+}  // namespace
+
+int nufft_tv_shrink(int d, const int64_t *N, const void *x_dev, void *d_dev, void *b_dev, float t, void *stream) {
+    int st = check_image(d, N);
+    if (st) return st;
+    if (!x_dev || !d_dev || !b_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    if (!(t >= 0.f) || !std::isfinite(t)) return fail(NUFFT_ERR_INVALID_ARG, "threshold must be finite and >= 0");
+    HIP_TRY(launch_tv_shrink(d, N, static_cast<const float2 *>(x_dev), static_cast<float2 *>(d_dev),
+                             static_cast<float2 *>(b_dev), t, static_cast<hipStream_t>(stream)),
+            "TV shrink");
+    return NUFFT_OK;
+}
+
+int nufft_tv_rhs(int d, const int64_t *N, float mu, const void *ahy_dev, const void *df_dev, const void *bf_dev,
+                 float lam, const void *d_dev, const void *b_dev, void *rhs_dev, void *stream) {
+    int st = check_image(d, N);
+    if (st) return st;
+    if (!ahy_dev || !d_dev || !b_dev || !rhs_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    if ((df_dev == nullptr) != (bf_dev == nullptr))
+        return fail(NUFFT_ERR_INVALID_ARG, "df and bf are given together or not at all");
+    HIP_TRY(launch_tv_rhs(d, N, mu, static_cast<const float2 *>(ahy_dev), static_cast<const float2 *>(df_dev),
+                          static_cast<const float2 *>(bf_dev), lam, static_cast<const float2 *>(d_dev),
+                          static_cast<const float2 *>(b_dev), static_cast<float2 *>(rhs_dev),
+                          static_cast<hipStream_t>(stream)),
+            "TV right-hand side");
+    return NUFFT_OK;
+}
+
+int nufft_tv_normal(int d, const int64_t *N, float mu, const void *ahax_dev, float lam, const void *x_dev,
+                    void *out_dev, void *stream) {
+    int st = check_image(d, N);
+    if (st) return st;
+    if (!ahax_dev || !x_dev || !out_dev) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    HIP_TRY(launch_tv_normal(d, N, mu, static_cast<const float2 *>(ahax_dev), lam, static_cast<const float2 *>(x_dev),
+                             static_cast<float2 *>(out_dev), static_cast<hipStream_t>(stream)),
+            "TV normal operator");
+    return NUFFT_OK;
+}
+
+int nufft_bregman_shrink(int64_t n, const void *r_dev, void *d_dev, void *b_dev, float t, void *stream) {
+    if (n < 0) return fail(NUFFT_ERR_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!r_dev || !d_dev || !b_dev)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
+    if (!(t >= 0.f) || !std::isfinite(t)) return fail(NUFFT_ERR_INVALID_ARG, "threshold must be finite and >= 0");
+    HIP_TRY(launch_bregman_shrink(n, static_cast<const float2 *>(r_dev), static_cast<float2 *>(d_dev),
+                                  static_cast<float2 *>(b_dev), t, static_cast<hipStream_t>(stream)),
+            "Bregman shrink");
+    return NUFFT_OK;
+}
 }  // extern "C"

@@ -1242,6 +1242,89 @@ __global__ __launch_bounds__(256) void k_real_to_complex(const float *w, float2 
     if (m < M) wc[m] = make_float2(w[m] * scale, 0.f);
 }
 
+// ------------------------------------------------------------ TV split-Bregman pieces
+// Image gradient grad_a x = x(.., i_a + 1, ..) - x(.., i_a, ..) with
+// wrap-around, its transpose g(.., i_a - 1, ..) - g(.., i_a, ..), and the
+// complex soft threshold shrink(z, t) = z / |z| * max(|z| - t, 0).  One
+// thread per pixel; every axis of the pixel in registers.
+struct TvGeom {
+    int d;
+    int64_t N[kMaxDim];
+    int64_t stride[kMaxDim];
+    int64_t n;
+};
+
+__device__ __forceinline__ float2 shrinkc(float2 z, float t) {
+    const float a = hypotf(z.x, z.y);
+    const float sc = a > t ? (a - t) / a : 0.f;
+    return make_float2(z.x * sc, z.y * sc);
+}
+
+// index of the pixel one step along axis a (delta = +1 or -1), wrapped
+__device__ __forceinline__ int64_t tv_step(const TvGeom &g, int64_t i, int a, int delta) {
+    const int64_t c = (i / g.stride[a]) % g.N[a];
+    int64_t c2 = c + delta;
+    if (c2 < 0) c2 += g.N[a];
+    if (c2 >= g.N[a]) c2 -= g.N[a];
+    return i + (c2 - c) * g.stride[a];
+}
+
+__global__ __launch_bounds__(256) void k_tv_shrink(TvGeom g, const float2 *x, float2 *dd, float2 *bb, float t) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const float2 xi = x[i];
+    for (int a = 0; a < g.d; ++a) {
+        const float2 xn = x[tv_step(g, i, a, +1)];
+        const int64_t k = int64_t(a) * g.n + i;
+        const float2 z = cadd(csub(xn, xi), bb[k]);
+        const float2 dv = shrinkc(z, t);
+        dd[k] = dv;
+        bb[k] = csub(z, dv);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tv_rhs(TvGeom g, float mu, const float2 *ahy, const float2 *df,
+                                                const float2 *bf, float lam, const float2 *dd, const float2 *bb,
+                                                float2 *rhs) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    float2 v = ahy[i];
+    if (df) v = cadd(v, csub(df[i], bf[i]));
+    float2 acc = cscale(v, mu);
+    for (int a = 0; a < g.d; ++a) {
+        const int64_t k = int64_t(a) * g.n;
+        const int64_t ip = tv_step(g, i, a, -1);
+        const float2 here = csub(dd[k + i], bb[k + i]);
+        const float2 prev = csub(dd[k + ip], bb[k + ip]);
+        acc = cadd(acc, cscale(csub(prev, here), lam));
+    }
+    rhs[i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_tv_normal(TvGeom g, float mu, const float2 *ahax, float lam, const float2 *x,
+                                                   float2 *out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const float2 xi = x[i];
+    float2 lap = make_float2(0.f, 0.f);
+    for (int a = 0; a < g.d; ++a) {
+        // grad^T grad along a: 2 x(i) - x(i - e_a) - x(i + e_a)
+        const float2 xm = x[tv_step(g, i, a, -1)];
+        const float2 xp = x[tv_step(g, i, a, +1)];
+        lap = cadd(lap, csub(csub(cscale(xi, 2.f), xm), xp));
+    }
+    out[i] = cadd(cscale(ahax[i], mu), cscale(lap, lam));
+}
+
+__global__ __launch_bounds__(256) void k_bregman_shrink(int64_t n, const float2 *r, float2 *dv, float2 *bv, float t) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 z = cadd(r[i], bv[i]);
+    const float2 dd = shrinkc(z, t);
+    dv[i] = dd;
+    bv[i] = csub(z, dd);
+}
+
 // ------------------------------------------------------------ template dispatch
 template <template <int, int> class Fn, int J>
 struct DimDispatch {
@@ -1512,6 +1595,49 @@ hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, fl
 hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s) {
     if (M == 0) return hipSuccess;
     hipLaunchKernelGGL(k_real_to_complex, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, wc, M, scale);
+    return hipGetLastError();
+}
+
+static TvGeom tv_geom(int d, const int64_t *N) {
+    TvGeom g{};
+    g.d = d;
+    int64_t st = 1;
+    for (int a = d - 1; a >= 0; --a) {
+        g.N[a] = N[a];
+        g.stride[a] = st;
+        st *= N[a];
+    }
+    g.n = st;
+    return g;
+}
+
+hipError_t launch_tv_shrink(int d, const int64_t *N, const float2 *x, float2 *dd, float2 *bb, float t, hipStream_t s) {
+    const TvGeom g = tv_geom(d, N);
+    if (g.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_shrink, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, x, dd, bb, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_rhs(int d, const int64_t *N, float mu, const float2 *ahy, const float2 *df, const float2 *bf,
+                         float lam, const float2 *dd, const float2 *bb, float2 *rhs, hipStream_t s) {
+    const TvGeom g = tv_geom(d, N);
+    if (g.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_rhs, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, mu, ahy, df, bf, lam, dd, bb,
+                       rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_normal(int d, const int64_t *N, float mu, const float2 *ahax, float lam, const float2 *x,
+                            float2 *out, hipStream_t s) {
+    const TvGeom g = tv_geom(d, N);
+    if (g.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_normal, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, mu, ahax, lam, x, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bregman_shrink(int64_t n, const float2 *r, float2 *dv, float2 *bv, float t, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bregman_shrink, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, r, dv, bv, t);
     return hipGetLastError();
 }
 

@@ -333,6 +333,12 @@ struct BinArgs {
 };
 hipError_t launch_bin_keys(const BinArgs &a, hipStream_t s);
 hipError_t launch_iota(int *v, int64_t n, hipStream_t s);
+hipError_t launch_tv_shrink(int d, const int64_t *N, const float2 *x, float2 *dd, float2 *bb, float t, hipStream_t s);
+hipError_t launch_tv_rhs(int d, const int64_t *N, float mu, const float2 *ahy, const float2 *df, const float2 *bf,
+                         float lam, const float2 *dd, const float2 *bb, float2 *rhs, hipStream_t s);
+hipError_t launch_tv_normal(int d, const int64_t *N, float mu, const float2 *ahax, float lam, const float2 *x,
+                            float2 *out, hipStream_t s);
+hipError_t launch_bregman_shrink(int64_t n, const float2 *r, float2 *dv, float2 *bv, float t, hipStream_t s);
 hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, float inv_c, hipStream_t s);
 hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s);
 hipError_t launch_permute_points(const float *om, const int *perm, int64_t M, int d, float *om_sorted,
