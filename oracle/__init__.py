@@ -464,3 +464,86 @@ def l1tv(y, om, N, K, J, mu: float, lam: float, outer: int, inner: int, cg_iters
                 bf = z - df
         ahyk = ahyk + ahy - AHA(x)
     return x
+
+
+# ------------------------------------------------------------------ min-max interpolator
+# The paper's default interpolator (Section 2.1 "Interpolation", after Fessler
+# and Sutton): for a sample at u = omega K / (2 pi) with first tap k0 (the
+# same window as the Kaiser-Bessel path), the J coefficients c minimise the
+# worst-case error over unit-norm images,
+#   || e^{-i omega n} - s_n sum_j c_j e^{-i gamma (k0 + j) n} ||_2 over n,
+# gamma = 2 pi / K, i.e. c = T^-1 r with
+#   T_jl = sum_n s_n^2 e^{i gamma (j - l) n},   r_j = sum_n s_n e^{-i gamma t_j n},
+# t_j = u - k0 - j, n over the image range [-N/2, N/2).  Scaling factors
+# (reading): the Kaiser-Bessel ones taken at the half-integer centres,
+# s_n = 1 / Phi((n + 1/2) / K), which makes the range of n + 1/2 symmetric.
+def minmax_scaling(N: int, K: int, J: int) -> np.ndarray:
+    beta = kb_beta(J, K / N)
+    n = np.arange(N) - N // 2
+    return np.array([1.0 / kb_ft((v + 0.5) / K, J, beta) for v in n])
+
+
+def minmax_coefs(om_a, N: int, K: int, J: int):
+    """Per sample of one axis: (k0, c) with c complex [M, J] = T^-1 r."""
+    om_a = np.asarray(om_a, np.float64)
+    s = minmax_scaling(N, K, J)
+    n = np.arange(N) - N // 2
+    g = 2.0 * np.pi / K
+    jj = np.arange(J)
+    T = (s[None, None, :] ** 2 * np.exp(1j * g * (jj[:, None, None] - jj[None, :, None]) * n[None, None, :])).sum(-1)
+    u = om_a * (K / (2.0 * np.pi))
+    k0 = np.floor(u - J / 2.0) + 1.0
+    t = u[:, None] - k0[:, None] - jj[None, :]                      # [M, J]
+    r = (s[None, None, :] * np.exp(-1j * g * t[:, :, None] * n[None, None, :])).sum(-1)   # [M, J]
+    c = np.linalg.solve(T[None], r[..., None])[..., 0]
+    return k0.astype(np.int64), c
+
+
+def _minmax_taps(om, N, K, J):
+    d = len(N)
+    per = [minmax_coefs(np.asarray(om)[:, a], N[a], K[a], J) for a in range(d)]
+    M = np.asarray(om).shape[0]
+    idx = np.zeros((M,) + (J,) * d, np.int64)
+    w = np.ones((M,) + (J,) * d, np.complex128)
+    for a in range(d):
+        k0, c = per[a]
+        shape = [M] + [1] * d
+        shape[a + 1] = J
+        kk = (k0[:, None] + np.arange(J)[None, :]) % K[a]
+        idx = idx * K[a] + kk.reshape(shape)
+        w = w * c.reshape(shape)
+    return idx.reshape(M, -1), w.reshape(M, -1)
+
+
+def minmax_forward(x, om, N, K, J) -> np.ndarray:
+    """y = V_mm F S_mm x: scale by the min-max scaling factors, zero-pad and
+    FFT (as the Kaiser-Bessel path), interpolate with the min-max
+    coefficients."""
+    N = tuple(int(v) for v in N)
+    S = np.ones(N)
+    for a in range(len(N)):
+        shape = [1] * len(N)
+        shape[a] = N[a]
+        S = S * minmax_scaling(N[a], K[a], J).reshape(shape)
+    xs = np.asarray(x, np.complex128).reshape(N) * S
+    G = np.zeros(tuple(K), np.complex128)
+    G[np.ix_(*[(np.arange(n) - n // 2) % k for n, k in zip(N, K)])] = xs
+    G = fftn(G, -1)
+    idx, w = _minmax_taps(om, N, K, J)
+    return (w * G.ravel()[idx]).sum(1)
+
+
+def minmax_adjoint(y, om, N, K, J) -> np.ndarray:
+    """x = S_mm^H F^H V_mm^H y (conjugate coefficients, inverse FFT, crop,
+    scale)."""
+    N = tuple(int(v) for v in N)
+    idx, w = _minmax_taps(om, N, K, J)
+    h = np.zeros(int(np.prod(K)), np.complex128)
+    np.add.at(h, idx.ravel(), (np.conj(w) * np.asarray(y, np.complex128)[:, None]).ravel())
+    H = fftn(h.reshape(tuple(K)), +1)
+    x = H[np.ix_(*[(np.arange(n) - n // 2) % k for n, k in zip(N, K)])]
+    for a in range(len(N)):
+        shape = [1] * len(N)
+        shape[a] = N[a]
+        x = x * minmax_scaling(N[a], K[a], J).reshape(shape)
+    return x
