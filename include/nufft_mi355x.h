@@ -99,6 +99,14 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *                 perimeter sum(tile) <= 61, else NUFFT_ERR_UNSUPPORTED);
  *                 2: on the vector ALUs; 0: matrix cores where the tile
  *                 allows it (d >= 2)
+ *   interpolator  0: Kaiser-Bessel (the workloads' kernel); 1: min-max (the
+ *                 paper's default, Section 2.1 "Interpolation", after Fessler
+ *                 and Sutton): per sample and axis the J coefficients that
+ *                 minimise the worst-case interpolation error over unit-norm
+ *                 images for the scaling factors 1/Phi((n + 1/2)/K), Phi the
+ *                 Kaiser-Bessel transform (the same J and beta).  With
+ *                 min-max, nufft_grad_points and nufft_density_compensation
+ *                 return NUFFT_ERR_UNSUPPORTED.
  * Other values give NUFFT_ERR_INVALID_ARG.
  * Used by the autotuner (paper_1710_03197_amd/autotune.py). */
 typedef struct {
@@ -109,7 +117,8 @@ typedef struct {
     int presort;
     int fuse_reduce;
     int grid_mfma;
-    int reserved[3];
+    int interpolator;
+    int reserved[2];
 } nufft_options_t;
 
 /* nufft_plan with tuning options (opt may be NULL = defaults). */

@@ -40,7 +40,8 @@ class PlanOptions(ctypes.Structure):
     """nufft_options_t of include/nufft_mi355x.h (0 = default)."""
     _fields_ = [("tile", ctypes.c_int * 3), ("grid_chunk", ctypes.c_int), ("fft_groups", ctypes.c_int),
                 ("interp_direct", ctypes.c_int), ("presort", ctypes.c_int),
-                ("fuse_reduce", ctypes.c_int), ("grid_mfma", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("fuse_reduce", ctypes.c_int), ("grid_mfma", ctypes.c_int), ("interpolator", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class ProblemDesc(ctypes.Structure):

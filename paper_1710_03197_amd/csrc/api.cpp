@@ -104,6 +104,8 @@ struct nufft_plan_s {
     // device constants
     float *scale[kMaxDim] = {nullptr, nullptr, nullptr};
     float2 *tw[kMaxDim] = {nullptr, nullptr, nullptr};
+    bool minmax = false;                                   // min-max interpolator
+    float2 *phase[kMaxDim] = {nullptr, nullptr, nullptr};  // its grid phase e^{-i pi k / K}
     float *coef[kMaxDim] = {nullptr, nullptr, nullptr};
     int nq[kMaxDim] = {0, 0, 0};
     int nq_d[kMaxDim] = {0, 0, 0};
@@ -155,6 +157,7 @@ struct nufft_plan_s {
         g.d = d;
         g.J = J;
         g.jp = coef_row_width(J);
+        g.minmax = minmax ? 1 : 0;
         for (int a = 0; a < d; ++a) {
             g.K[a] = int(K[a]);
             g.C[a] = double(K[a]) / (2.0 * kPi);
@@ -225,6 +228,7 @@ void free_plan(nufft_plan_s *p) {
         dfree(p->tw[a]);
         dfree(p->coef[a]);
         dfree(p->dcoef[a]);
+        dfree(p->phase[a]);
     }
     dfree(p->om);
     dfree(p->om_sorted);
@@ -439,6 +443,7 @@ struct FftGeom {
     const RadixPlan *rp = nullptr;  // [d]
     float2 *const *tw = nullptr;    // [d]
     float *const *scale = nullptr;  // [d]
+    float2 *const *phase = nullptr; // [d] min-max grid phase, or nullptr
     const float2 *coils = nullptr;  // [C][N^d] in coil mode, else nullptr
     int C = 1;
     float2 *grid = nullptr;
@@ -456,6 +461,7 @@ FftGeom plan_fft(const nufft_plan_s *p) {
     f.rp = p->rp;
     f.tw = p->tw;
     f.scale = p->scale;
+    f.phase = p->minmax ? p->phase : nullptr;
     f.coils = p->coil_mode ? p->coils : nullptr;
     f.C = p->coil_mode ? p->C : 1;
     f.grid = p->grid;
@@ -491,6 +497,7 @@ int run_fs(nufft_plan_s *p, const FftGeom &f, const float2 *x, int B, float2 *ou
             a.d = d;
             a.target_groups = f.fft_groups;
             a.mult = (d == 1) ? mult : nullptr;
+            a.phase = f.phase ? f.phase[ax] : nullptr;
             for (int b = 0; b < d; ++b) {
                 a.Nax[b] = int(f.N[b]);
                 a.scale[b] = f.scale[b];
@@ -512,6 +519,7 @@ int run_fs(nufft_plan_s *p, const FftGeom &f, const float2 *x, int B, float2 *ou
             a.grids = grids;
             a.inverse = false;
             a.target_groups = f.fft_groups;
+            a.phase = f.phase ? f.phase[ax] : nullptr;
             HIP_TRY(timed(p, kStridedFwd, s, [&] { return launch_strided_pass(a, s); }), "forward strided FFT pass");
         }
         cur = dst;
@@ -544,6 +552,7 @@ int run_shfh(nufft_plan_s *p, const FftGeom &f, const float2 *h, int B, float2 *
             for (int b = 0; b < d - 1; ++b) a.rows *= f.N[b];
             a.d = d;
             a.target_groups = f.fft_groups;
+            a.phase = f.phase ? f.phase[ax] : nullptr;
             for (int b = 0; b < d; ++b) {
                 a.Nax[b] = int(f.N[b]);
                 a.scale[b] = f.scale[b];
@@ -566,6 +575,7 @@ int run_shfh(nufft_plan_s *p, const FftGeom &f, const float2 *h, int B, float2 *
             a.grids = grids;
             a.inverse = true;
             a.target_groups = f.fft_groups;
+            a.phase = f.phase ? f.phase[ax] : nullptr;
             if (ax == 0) a.mult = mult;
             if (ax == 0 && fused_partials && p->n_hot > 0) {
                 a.hot_of_tile = p->hot_of_tile;
@@ -1043,8 +1053,12 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     const int need = J - 1;
     p->tile_cells = 1;
     p->nbins = 1;
+    if (opt && (opt->interpolator < 0 || opt->interpolator > 1))
+        return bail(fail(NUFFT_ERR_INVALID_ARG, "interpolator takes 0 (Kaiser-Bessel) or 1 (min-max)"));
+    p->minmax = opt && opt->interpolator == 1;
     for (int a = 0; a < d; ++a) {
-        if (!kb_fit(J, kb_beta(J, double(K[a]) / double(N[a])), &p->ker[a]))
+        const double beta = kb_beta(J, double(K[a]) / double(N[a]));
+        if (p->minmax ? !minmax_fit(int(N[a]), int(K[a]), J, beta, &p->ker[a]) : !kb_fit(J, beta, &p->ker[a]))
             return bail(fail(NUFFT_ERR_UNSUPPORTED, "kernel polynomial fit did not converge"));
         if (!radix_plan(int(K[a]), &p->rp[a])) return bail(fail(NUFFT_ERR_UNSUPPORTED, "no radix plan for K"));
         const int target = (opt && opt->tile[a] > 0) ? opt->tile[a] : targets[d - 1][a];
@@ -1055,7 +1069,9 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         p->nbins *= p->nt[a];
         int st;
         hipError_t e;
-        if ((e = upload(&p->scale[a], kb_scaling(int(N[a]), int(K[a]), J, p->ker[a].beta))) != hipSuccess ||
+        if ((e = upload(&p->scale[a], p->minmax ? minmax_scaling(int(N[a]), int(K[a]), J, beta)
+                                                : kb_scaling(int(N[a]), int(K[a]), J, beta))) != hipSuccess ||
+            (p->minmax && (e = upload(&p->phase[a], half_phase(int(K[a])))) != hipSuccess) ||
             (e = upload(&p->tw[a], twiddles(int(K[a])))) != hipSuccess ||
             (e = upload(&p->coef[a], coef_rows(p->ker[a].coef, J, p->ker[a].deg, coef_row_width(J), &p->nq[a]))) !=
                 hipSuccess ||
@@ -1252,6 +1268,7 @@ int nufft_adjoint(nufft_plan_t plan, const void *y_dev, void *x_dev, void *strea
 int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev, float *gom_dev, void *stream) {
     int st = begin_call(plan, stream);
     if (st) return st;
+    if (plan->minmax) return fail(NUFFT_ERR_UNSUPPORTED, "trajectory gradients need the Kaiser-Bessel interpolator");
     if (!x_dev || ((!gy_dev || !gom_dev) && plan->M > 0)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
     const int C = plan->coil_mode ? plan->C : 1;
     if ((st = ensure_workspace(plan, C))) return st;
@@ -1509,6 +1526,7 @@ int nufft_toeplitz_destroy(nufft_toeplitz_t t) {
 int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void *stream) {
     int st = begin_call(plan, stream);
     if (st) return st;
+    if (plan->minmax) return fail(NUFFT_ERR_UNSUPPORTED, "density compensation needs the Kaiser-Bessel interpolator");
     if (iters < 0) return fail(NUFFT_ERR_INVALID_ARG, "iters must be >= 0");
     if (plan->M > 0 && !w_dev) return fail(NUFFT_ERR_INVALID_ARG, "w is NULL");
     if (plan->M == 0 || iters == 0) return NUFFT_OK;

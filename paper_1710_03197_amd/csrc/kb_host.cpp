@@ -6,6 +6,7 @@
 // (Section 2.1 "Oversampled FFT").
 #include <cmath>
 #include <cstring>
+#include <map>
 
 #include "nufft_internal.h"
 
@@ -117,16 +118,16 @@ static double horner64(const double *c, int deg, double z) {
     return v;
 }
 
-// Fit w_j(z) = phi(t), t = (z+1)/2 + J/2 - 1 - j, for every tap j, with
-// the lowest degree whose float64 error is below `tol` (relative to the peak
-// of the fitted function).
+// Fit w_j(z) = fn(j, f), f = (z+1)/2 the window's fractional offset, for
+// every tap j, with the lowest degree whose float64 error is below `tol`
+// (relative to the peak of the fitted function).
 template <class F>
-static int fit_taps(int J, F fn, double peak, double tol, std::vector<float> *out) {
+static int fit_taps_jf(int J, F fn, double peak, double tol, std::vector<float> *out) {
     for (int deg = 4; deg <= kMaxPolyDeg; ++deg) {
         std::vector<double> c(size_t(J) * (deg + 1));
         double err = 0.0;
         for (int j = 0; j < J; ++j) {
-            auto g = [&](double z) { return fn((z + 1.0) * 0.5 + 0.5 * J - 1.0 - j); };
+            auto g = [&](double z) { return fn(j, (z + 1.0) * 0.5); };
             cheb_fit(g, deg, &c[size_t(j) * (deg + 1)]);
             for (int s = 0; s <= 400; ++s) {
                 double z = -1.0 + 2.0 * s / 400.0;
@@ -141,6 +142,13 @@ static int fit_taps(int J, F fn, double peak, double tol, std::vector<float> *ou
         }
     }
     return -1;
+}
+
+// The Kaiser-Bessel taps are one function of the tap offset
+// t = f + J/2 - 1 - j.
+template <class F>
+static int fit_taps(int J, F fn, double peak, double tol, std::vector<float> *out) {
+    return fit_taps_jf(J, [&](int j, double f) { return fn(f + 0.5 * J - 1.0 - j); }, peak, tol, out);
 }
 
 bool kb_fit(int J, double beta, AxisKernel *out) {
@@ -172,6 +180,102 @@ void kb_eval_fit(const AxisKernel &k, int J, float f, float *w, float *dw) {
             dw[j] = u;
         }
     }
+}
+
+// ---- min-max interpolator (Section 2.1 "Interpolation", after Fessler and
+// Sutton).  With the scaling factors s_n = g(n + 1/2), g(m) = 1/Phi(m/K),
+// n in [-N/2, N/2), the worst-case-optimal coefficients c = T^-1 r factor as
+// c_j = e^{i gamma t_j / 2} c'_j with c' real:
+//   c' = T'^-1 R'(t),  T'_jl = sum_m g(m)^2 cos(gamma (j - l) m),
+//   R'(t)_j = sum_m g(m) cos(gamma t_j m),  gamma = 2 pi / K,
+// m over the symmetric half-integers n + 1/2, t_j = f + J/2 - 1 - j.  The
+// phase e^{i gamma t_j / 2} = e^{i omega / 2} e^{-i pi k / K} (k = k0 + j
+// unwrapped) is applied by the kernels: e^{-i pi k / K} on the grid (FFT
+// passes, half_phase) with a sign for taps that wrap past K, e^{i omega / 2}
+// per sample.
+std::vector<float> minmax_scaling(int N, int K, int J, double beta) {
+    std::vector<float> s(N);
+    for (int i = 0; i < N; ++i) s[i] = float(1.0 / kb_ft((double(i - N / 2) + 0.5) / K, J, beta));
+    return s;
+}
+
+std::vector<float2> half_phase(int K) {
+    std::vector<float2> p(K);
+    for (int k = 0; k < K; ++k) {
+        const double a = -kPi * double(k) / double(K);
+        p[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    }
+    return p;
+}
+
+// Solve A x = b (n x n, row-major) by Gaussian elimination with partial
+// pivoting; A and b are overwritten.
+static bool solve_dense(int n, std::vector<double> &A, std::vector<double> &b) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[size_t(r) * n + c]) > std::fabs(A[size_t(piv) * n + c])) piv = r;
+        if (A[size_t(piv) * n + c] == 0.0) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[size_t(c) * n + k], A[size_t(piv) * n + k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[size_t(r) * n + c] / A[size_t(c) * n + c];
+            for (int k = c; k < n; ++k) A[size_t(r) * n + k] -= f * A[size_t(c) * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double v = b[c];
+        for (int k = c + 1; k < n; ++k) v -= A[size_t(c) * n + k] * b[k];
+        b[c] = v / A[size_t(c) * n + c];
+    }
+    return true;
+}
+
+bool minmax_fit(int N, int K, int J, double beta, AxisKernel *out) {
+    std::vector<double> g(N), m(N);
+    for (int i = 0; i < N; ++i) {
+        m[i] = double(i - N / 2) + 0.5;
+        g[i] = 1.0 / kb_ft(m[i] / K, J, beta);
+    }
+    const double gam = 2.0 * kPi / K;
+    std::vector<double> T(size_t(J) * J);
+    for (int j = 0; j < J; ++j)
+        for (int l = 0; l < J; ++l) {
+            double v = 0.0;
+            for (int i = 0; i < N; ++i) v += g[i] * g[i] * std::cos(gam * (j - l) * m[i]);
+            T[size_t(j) * J + l] = v;
+        }
+    bool ok = true;
+    // c'(f) for all taps at once, memoised: the fit asks for every tap at the
+    // same offsets
+    std::map<double, std::vector<double>> memo;
+    auto coef = [&](int j, double f) {
+        auto it = memo.find(f);
+        if (it == memo.end()) {
+            std::vector<double> A = T, r(J);
+            for (int l = 0; l < J; ++l) {
+                const double t = f + 0.5 * J - 1.0 - l;
+                double v = 0.0;
+                for (int i = 0; i < N; ++i) v += g[i] * std::cos(gam * t * m[i]);
+                r[l] = v;
+            }
+            if (!solve_dense(J, A, r)) ok = false;
+            it = memo.emplace(f, std::move(r)).first;
+        }
+        return it->second[j];
+    };
+    double peak = 0.0;
+    for (int s = 0; s <= 200; ++s)
+        for (int j = 0; j < J; ++j) peak = std::fmax(peak, std::fabs(coef(j, s / 200.0)));
+    out->beta = beta;
+    out->deg = fit_taps_jf(J, coef, peak, 2e-9, &out->coef);
+    // no derivative fit: the trajectory gradient is Kaiser-Bessel only
+    out->deg_d = 1;
+    out->dcoef.assign(size_t(J) * 2, 0.0f);
+    return ok && out->deg > 0;
 }
 
 std::vector<float> coef_rows(const std::vector<float> &coef, int J, int deg, int jp, int *nq) {

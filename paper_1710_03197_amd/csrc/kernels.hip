@@ -268,11 +268,13 @@ __global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lin
     __syncthreads();
     lds_fft<THREADS, false, false>(s, nl, K, K, 1, a.rp, tw);
     float2 *out = a.out + l0 * K;
-    if (a.mult) {
+    if (a.mult || a.phase) {
         for (int e = threadIdx.x; e < nl * K; e += THREADS) {
             const int lw = e / K, q = e - lw * K;
-            const int64_t r = (l0 + lw) % a.rows;
-            out[e] = cmul(s[e], a.mult[r * K + q]);
+            float2 v = s[e];
+            if (a.phase) v = cmul(v, a.phase[q]);
+            if (a.mult) v = cmul(v, a.mult[((l0 + lw) % a.rows) * K + q]);
+            out[e] = v;
         }
     } else {
         for (int e = threadIdx.x; e < nl * K; e += THREADS) out[e] = s[e];
@@ -329,6 +331,7 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
                     const float2 *pp = a.partials + (g * a.n_slots + ht.slot) * a.tile_cells + cell;
                     for (int k = 0; k < ht.nchunks; ++k) v = cadd(v, pp[int64_t(k) * a.tile_cells]);
                 }
+                if (INV && a.phase) v = cmulcj(a.phase[q], v);
             }
         }
         s[e] = v;
@@ -339,7 +342,9 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
         const int i = e / W, w = e - i * W;
         if (w < wv) {
             const int q = INV ? pad_pos(i, a.Lout, K) : i;
-            out[int64_t(i) * a.inner + w] = s[q * W + w];
+            float2 v = s[q * W + w];
+            if (!INV && a.phase) v = cmul(v, a.phase[q]);
+            out[int64_t(i) * a.inner + w] = v;
         }
     }
 }
@@ -369,7 +374,9 @@ __global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_
         for (int e = threadIdx.x; e < nl * K; e += THREADS) {
             const int lw = e / K, q = e - lw * K;
             const int rr = lw / nc, cc = lw - rr * nc;
-            s[e] = a.in[((b * C + c0 + cc) * a.rows + r0 + rr) * K + q];
+            float2 v = a.in[((b * C + c0 + cc) * a.rows + r0 + rr) * K + q];
+            if (a.phase) v = cmulcj(a.phase[q], v);
+            s[e] = v;
         }
         __syncthreads();
         lds_fft<THREADS, true, false>(s, nl, K, K, 1, a.rp, tw);
@@ -415,6 +422,43 @@ __device__ __forceinline__ float window_pos(const SampleGeom &geo, int ax, float
         kk[j] = k >= K ? k - K : k;
     }
     return f;
+}
+
+// Min-max interpolator: the coefficients are c_j = e^{i gamma t_j / 2} c'_j
+// with c' the real fitted factors, and e^{i gamma t_j / 2} =
+// e^{i omega / 2} (-1)^{floor(k0 / K)} (-1)^{[k0 mod K + j >= K]} e^{-i pi k_w / K}
+// (k_w the wrapped grid index).  The FFT passes apply e^{-i pi k_w / K}; the
+// sample kernels apply the rest: this per-sample phase (float64 angle) and a
+// sign on taps that wrap past K.
+template <int DIM>
+__device__ __forceinline__ float2 mm_phase(const SampleGeom &geo, const float *om) {
+    double ang = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        const double u = __dmul_rn(double(om[ax]), geo.C[ax]);
+        const double k0 = floor(u - 0.5 * geo.J) + 1.0;
+        ang += 0.5 * double(om[ax]) + 3.141592653589793 * floor(k0 / double(geo.K[ax]));
+    }
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    return make_float2(float(cs), float(sn));
+}
+
+// First tap index j that wraps past K on axis `ax` (J or more: none).
+__device__ __forceinline__ int mm_wrap_from(const SampleGeom &geo, int ax, float om) {
+    const double u = __dmul_rn(double(om), geo.C[ax]);
+    const double k0 = floor(u - 0.5 * geo.J) + 1.0;
+    const int K = geo.K[ax];
+    long long kw = static_cast<long long>(k0) % K;
+    if (kw < 0) kw += K;
+    return K - int(kw);
+}
+
+template <int NJ>
+__device__ __forceinline__ void mm_sign_taps(float *w, int wrap_from) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        if (j >= wrap_from) w[j] = -w[j];
 }
 
 // Per-tap polynomials of the kernel fit: NJ Horner chains in z over the
@@ -482,11 +526,13 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
     float w[SPT][DIM][J];
     int off[SPT];
     bool valid[SPT];
+    float2 ph[SPT];
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const int s = threadIdx.x + k * 256;
         valid[k] = s < it.count;
         off[k] = 0;
+        ph[k] = make_float2(1.f, 0.f);
         if (valid[k]) {
             const int64_t i = it.start + s;
             int o = 0;
@@ -495,9 +541,11 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
                 int kk[J];
                 const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk);
                 window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[k][ax]);
+                if (a.geo.minmax) mm_sign_taps<J>(w[k][ax], mm_wrap_from(a.geo, ax, a.om_sorted[i * DIM + ax]));
                 o = o * E[ax] + (kk[0] - base[ax]);
             }
             off[k] = o;
+            if (a.geo.minmax) ph[k] = mm_phase<DIM>(a.geo, a.om_sorted + i * DIM);
         }
     }
     for (int g = 0; g < a.grids; ++g) {
@@ -552,6 +600,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
                     acc = cadd(acc, cscale(ps, w[k][0][j0]));
                 }
             }
+            if (a.geo.minmax) acc = cmul(acc, ph[k]);
             a.y[int64_t(g) * a.M + a.perm[it.start + threadIdx.x + k * 256]] = acc;
         }
     }
@@ -569,7 +618,9 @@ __global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
     for (int ax = 0; ax < DIM; ++ax) {
         const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk[ax]);
         window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[ax]);
+        if (a.geo.minmax) mm_sign_taps<J>(w[ax], mm_wrap_from(a.geo, ax, a.om_sorted[i * DIM + ax]));
     }
+    const float2 ph = a.geo.minmax ? mm_phase<DIM>(a.geo, a.om_sorted + i * DIM) : make_float2(1.f, 0.f);
     const int64_t m = a.perm[i];
     for (int g = 0; g < a.grids; ++g) {
         const float2 *G = a.G + int64_t(g) * a.grid_elems;
@@ -602,6 +653,7 @@ __global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
                 acc = cadd(acc, cscale(ps, w[0][j0]));
             }
         }
+        if (a.geo.minmax) acc = cmul(acc, ph);
         a.y[int64_t(g) * a.M + m] = acc;
     }
 }
@@ -752,6 +804,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
 #pragma unroll
             for (int ax = 0; ax < DIM; ++ax) {
                 const double u = __dmul_rn(double(a.om_sorted[i * DIM + ax]), a.geo.C[ax]);
+                // (min-max: taps wrapping past K carry a sign, see mm_phase)
                 const double k0 = floor(u - 0.5 * J) + 1.0;
                 const float fr = float(u - k0 - (0.5 * J - 1.0));
                 const int K = a.geo.K[ax];
@@ -762,6 +815,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                 const float z = 2.0f * fr - 1.0f;
                 float wv[JP];
                 poly_rows<JP>(a.geo.coef[ax], JP, a.geo.nq[ax], z, wv);
+                if (a.geo.minmax) mm_sign_taps<JP>(wv, K - int(kw));
 #pragma unroll
                 for (int j = 0; j < JP; ++j) {
                     if (j < J) {
@@ -794,7 +848,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                 }
                 wr4[c4 >> 2] = make_float4(r[0], r[1], r[2], r[3]);
             }
-            const float2 v = a.y_sorted ? y[i] : y[a.perm[i]];
+            float2 v = a.y_sorted ? y[i] : y[a.perm[i]];
+            if (a.geo.minmax) v = cmulcj(mm_phase<DIM>(a.geo, a.om_sorted + i * DIM), v);
             sv[lane] = v.x;
             sv[BP + lane] = v.y;
         }
@@ -978,6 +1033,7 @@ __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
     for (int b0 = 0; b0 < n; b0 += 256) {
         // ---- stage: lane = sample b0 + 64 * wave + lane of the item
         float *my = rec + lane * RS;
+        if (pvalid && a.geo.minmax) pv = cmulcj(mm_phase<DIM>(a.geo, pom), pv);
         my[0] = pvalid ? pv.x : 0.f;
         my[1] = pvalid ? pv.y : 0.f;
 #pragma unroll
@@ -996,6 +1052,7 @@ __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
                 const int o = int(kw) - base[ax];  // first tap relative to the tile, in [-base, K - base)
                 float wv[NJ];
                 poly_rows<NJ>(a.geo.coef[ax], a.geo.jp, a.geo.nq[ax], 2.0f * fr - 1.0f, wv);
+                if (a.geo.minmax) mm_sign_taps<NJ>(wv, K - int(kw));
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
                     if (j < J) {

@@ -57,6 +57,12 @@ void kb_eval_fit(const AxisKernel &k, int J, float f, float *w, float *dw);
 std::vector<float> coef_rows(const std::vector<float> &coef, int J, int deg, int jp, int *nq);
 // Row width for J taps: 8 for J <= 8, else 16.
 inline int coef_row_width(int J) { return J <= 8 ? 8 : 16; }
+// Min-max interpolator of one axis (real factor c' of the coefficients per
+// tap; see kb_host.cpp), its scaling table 1 / Phi((i - N/2 + 1/2)/K), and
+// the grid phase e^{-i pi k / K}, k in [0, K).
+bool minmax_fit(int N, int K, int J, double beta, AxisKernel *out);
+std::vector<float> minmax_scaling(int N, int K, int J, double beta);
+std::vector<float2> half_phase(int K);
 // Scaling table s(i) = 1 / Phi((i - N/2)/K), i in [0, N) (float32).
 std::vector<float> kb_scaling(int N, int K, int J, double beta);
 // Twiddles e^{-2 pi i e / K}, e in [0, K), computed in float64.
@@ -83,6 +89,7 @@ struct FirstPassArgs {
     const float *scale[kMaxDim];
     const float2 *mult;  // d = 1 Toeplitz product: the output line times mult[q] (nullptr: none)
     int target_groups;  // workgroups the launch aims for
+    const float2 *phase;  // min-max grid phase e^{-i pi k / K} of this pass's axis (nullptr: none)
 };
 hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s);
 
@@ -111,6 +118,7 @@ struct StridedPassArgs {
     int Kax[kMaxDim];
     int T[kMaxDim];
     int nt[kMaxDim];
+    const float2 *phase;  // min-max grid phase e^{-i pi k / K} of this pass's axis (nullptr: none)
 };
 hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s);
 
@@ -129,6 +137,7 @@ struct LastPassArgs {
     int Nax[kMaxDim];
     const float *scale[kMaxDim];
     int target_groups;
+    const float2 *phase;  // min-max grid phase e^{-i pi k / K} of this pass's axis (nullptr: none)
 };
 hipError_t launch_last_pass(const LastPassArgs &a, hipStream_t s);
 
@@ -143,6 +152,8 @@ struct SampleGeom {
     int nq_d[kMaxDim];    // coefficient rows of the derivative fit
     const float *coef[kMaxDim];   // [nq][jp], highest degree first (coef_rows)
     const float *dcoef[kMaxDim];  // [nq_d][jp]
+    int minmax;           // min-max interpolator: real factors c' in coef, plus
+                          // the per-sample phase e^{i sum omega/2} and tap signs
 };
 
 // Interpolation V: y[g][perm[i]] = sum_taps w * G[g][..] for sorted sample i.

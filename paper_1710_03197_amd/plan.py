@@ -68,6 +68,9 @@ class Plan:
         opt.presort = int(self.options.get("presort", 0))
         opt.fuse_reduce = int(self.options.get("fuse_reduce", 0))
         opt.grid_mfma = int(self.options.get("grid_mfma", 0))
+        interp = self.options.get("interpolator", 0)
+        opt.interpolator = {"kb": 0, "kaiser-bessel": 0, "minmax": 1, "min-max": 1}.get(interp, interp) \
+            if isinstance(interp, str) else int(interp)
         with torch.cuda.device(self.device):
             _lib.call("nufft_plan_ex", d, n_arr, k_arr, self.J, self.M,
                       _ptr(om) if self.M else ctypes.c_void_p(), ctypes.byref(opt), _stream(self.device),
