@@ -239,9 +239,23 @@ def bench_2d(dev, steps, warmup, orc_mod, tune="cache", no_graph=False):
     toep = time_toeplitz(plan, x, xa, steps, warmup, sec)
     alg = algorithmic_bytes(N, K, M, J)
     info = plan.info()
+    opts = dict((tuned or {}).get("options") or {})
     plan.close()
+    # the paper's default interpolator (min-max) on the same workload: parity
+    # on 2048 sampled outputs against the oracle's direct definition, then time
+    pm = Plan(torch.from_numpy(om).to(dev), N, K, J, options=dict(opts, interpolator="minmax"))
+    pm.forward(x, out=y)
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(0).choice(M, 2048, replace=False)
+    err_mm = rel_l2(y.cpu().numpy()[pick], orc_mod.minmax_forward(c["x"], om[pick], N, K, J))
+    if not err_mm <= TOL:
+        raise SystemExit(f"min-max parity gate failed: {err_mm:.2e}")
+    sec_mm = time_pairs(pm, x, y, xa, steps, warmup)
+    pm.close()
+    minmax = {"pairs_per_s": round(1.0 / sec_mm, 2), "ms_per_pair": round(sec_mm * 1e3, 4),
+              "rel_err_forward_sampled": err_mm}
     return dict(sec=sec, sec_graph=sec_graph, ktimes=ktimes, alg=alg, err_f=err_f, err_a=err_a, N=N, K=K, M=M,
-                J=J, info=info, tuned=tuned, toeplitz=toep)
+                J=J, info=info, tuned=tuned, toeplitz=toep, minmax=minmax)
 
 
 def bench_3d(dev, steps, warmup, orc_mod, tune="cache"):
@@ -390,6 +404,7 @@ def main():
         "pair_model_frac": round(sum(r2["alg"].values()) / r2["sec"] / 1e9 / HBM_PEAK_GBS, 4),
         "plan": r2["info"], "kernels_sha": khash, "tuning": r2["tuned"],
         "toeplitz_normal_2d": r2["toeplitz"],
+        "minmax_interpolator_2d": r2["minmax"],
     }
     if not args.no_3d:
         r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod, tune=args.tune)
