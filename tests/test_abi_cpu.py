@@ -91,3 +91,47 @@ def test_kernel_fit_rejects_bad_arguments():
     dp = ctypes.POINTER(ctypes.c_double)
     assert lib.nufft_kernel_weights_host(1, 2.0, 3, f.ctypes.data_as(dp), w.ctypes.data_as(dp), None) == -1
     assert lib.nufft_kernel_weights_host(6, 0.5, 3, f.ctypes.data_as(dp), w.ctypes.data_as(dp), None) == -1
+
+
+def test_new_entry_points_reject_bad_handles():
+    """The Toeplitz operator, density compensation and the TV kernels validate
+    their handles and arguments on the host (no device is touched)."""
+    vp = ctypes.c_void_p
+    assert lib.nufft_toeplitz_apply(vp(), 1, vp(), vp(), vp()) == -5
+    assert lib.nufft_toeplitz_destroy(vp()) == -5
+    assert lib.nufft_toeplitz_destroy(vp(0x1234)) == -5
+    out = vp()
+    assert lib.nufft_toeplitz_plan(vp(), vp(), vp(), ctypes.byref(out)) == -5
+    assert lib.nufft_toeplitz_plan(vp(0x10), vp(), vp(), ctypes.byref(out)) == -5
+    assert lib.nufft_density_compensation(vp(), 3, vp(), vp()) == -5
+
+
+@pytest.mark.parametrize("d,N,t,code", [
+    (0, (8,), 1.0, -1),
+    (4, (8, 8, 8, 8), 1.0, -1),
+    (2, (8, 0), 1.0, -1),
+    (2, (8, 8), -1.0, -1),
+    (2, (8, 8), float("nan"), -1),
+])
+def test_tv_kernels_validate_arguments(d, N, t, code):
+    n = (ctypes.c_int64 * len(N))(*N)
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    f = ctypes.c_float
+    assert lib.nufft_tv_shrink(d, n, dummy, dummy, dummy, f(t), ctypes.c_void_p()) == code
+    if t >= 0:  # the threshold only matters to the shrink calls
+        assert lib.nufft_tv_normal(d, n, f(1.0), dummy, f(1.0), dummy, dummy, ctypes.c_void_p()) == code
+        assert lib.nufft_tv_rhs(d, n, f(1.0), dummy, None, None, f(1.0), dummy, dummy, dummy,
+                                ctypes.c_void_p()) == code
+
+
+def test_tv_kernels_reject_null_and_half_lad_arguments():
+    n = (ctypes.c_int64 * 2)(8, 8)
+    dummy = ctypes.c_void_p(0x1000)
+    f = ctypes.c_float
+    assert lib.nufft_tv_shrink(2, n, None, dummy, dummy, f(1.0), None) == -1
+    assert lib.nufft_tv_normal(2, n, f(1.0), None, f(1.0), dummy, dummy, None) == -1
+    # df without bf (or the reverse) is an error
+    assert lib.nufft_tv_rhs(2, n, f(1.0), dummy, dummy, None, f(1.0), dummy, dummy, dummy, None) == -1
+    assert lib.nufft_bregman_shrink(ctypes.c_int64(-1), dummy, dummy, dummy, f(1.0), None) == -1
+    assert lib.nufft_bregman_shrink(ctypes.c_int64(0), None, None, None, f(1.0), None) == 0
+    assert lib.nufft_bregman_shrink(ctypes.c_int64(4), dummy, dummy, dummy, f(-2.0), None) == -1

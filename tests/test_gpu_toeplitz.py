@@ -125,3 +125,23 @@ def test_toeplitz_rejects_bad_input(dev):
         w = torch.full((om.shape[0],), float("nan"), device=dev)
         with pytest.raises(NufftError):
             p.toeplitz(w)
+
+
+def test_toeplitz_empty_trajectory_and_growing_batches(dev):
+    """No samples: the operator is zero.  A larger batch after a smaller one
+    grows the workspace and gives the same per-image results."""
+    from paper_1710_03197_amd import Plan
+    N, K = (16, 12), (32, 24)
+    with Plan(torch.empty((0, 2), dtype=torch.float32, device=dev), N, K, 6) as p:
+        with p.toeplitz() as T:
+            out = T(_t(_rand_c(N, 1), dev)).cpu().numpy()
+        assert np.abs(out).max() == 0.0
+        assert p.density_compensation(3).numel() == 0
+    om = np.random.default_rng(2).uniform(-np.pi, np.pi, (700, 2)).astype(np.float32)
+    with Plan(_t(om, dev), N, K, 6) as p:
+        with p.toeplitz() as T:
+            x1 = _rand_c((1,) + N, 3)
+            o1 = T(_t(x1, dev)).cpu().numpy()
+            x5 = np.concatenate([x1, np.stack([_rand_c(N, 10 + b) for b in range(4)])])
+            o5 = T(_t(x5, dev)).cpu().numpy()
+    assert np.array_equal(o1[0], o5[0])
