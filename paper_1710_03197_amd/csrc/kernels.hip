@@ -114,6 +114,18 @@ __device__ __forceinline__ void dft<8>(float2 *v) {
     v[7] = csub(e[3], o3);
 }
 
+// floor(e / D) for 0 <= e < 2^16 by a divisor 1 <= D < 2^16 fixed per launch:
+// q = floor(e m / 2^32) with m = ceil(2^32 / D) is exact because e D < 2^32
+// keeps the error e (m D - 2^32) / (D 2^32) below 1/D.  One high multiply
+// instead of an integer division.
+struct FastDiv {
+    unsigned m;
+    int d;
+    __device__ __forceinline__ explicit FastDiv(int D) : m(D > 1 ? 0xFFFFFFFFu / unsigned(D) + 1u : 0u), d(D) {}
+    __device__ __forceinline__ int div(int e) const { return d > 1 ? int(__umulhi(unsigned(e), m)) : e; }
+    __device__ __forceinline__ int rem(int e, int q) const { return e - __umul24(q, d); }
+};
+
 // ------------------------------------------------------------ Stockham passes in LDS
 // Element (line, q) of a tile lives at s[line * LS + q * ES].  STRIDED tiles
 // keep lines adjacent (ES = number of lines) so a wavefront's lanes walk
@@ -129,6 +141,7 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
     constexpr int NB = (kEPT + R - 1) / R;
     const int nbl = K / R;
     const int total = nlines * nbl;
+    const FastDiv by_line(STRIDED ? nlines : nbl), by_ns(Ns);
     float2 v[NB][R];
     int lidx[NB], jidx[NB];
 #pragma unroll
@@ -139,11 +152,11 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
         if (b < total) {
             int line, j;
             if (STRIDED) {
-                line = b % nlines;
-                j = b / nlines;
+                j = by_line.div(b);
+                line = by_line.rem(b, j);
             } else {
-                j = b % nbl;
-                line = b / nbl;
+                line = by_line.div(b);
+                j = by_line.rem(b, line);
             }
             lidx[it] = line;
             jidx[it] = j;
@@ -159,8 +172,9 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
         const int b = threadIdx.x + it * THREADS;
         if (b < total) {
             const int j = jidx[it];
-            const int k = j % Ns;
-            const int step = k * span;
+            const int jq = by_ns.div(j);
+            const int k = by_ns.rem(j, jq);
+            const int step = __umul24(k, span);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 float2 w = tw[r * step];
@@ -176,7 +190,7 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[it][r].y = -v[it][r].y;
             }
-            const int idxD = (j / Ns) * Ns * R + k;
+            const int idxD = __umul24(jq, Ns * R) + k;
             float2 *q = s + lidx[it] * LS + idxD * ES;
 #pragma unroll
             for (int r = 0; r < R; ++r) q[r * Ns * ES] = v[it][r];
@@ -202,10 +216,28 @@ __device__ void lds_fft(float2 *s, int nlines, int K, int LS, int ES, const Radi
     }
 }
 
+// Twiddles into LDS.  A workgroup's tile holds at least one whole line, so a
+// thread stages at most kEPT of the K twiddles; every load is issued before
+// the first LDS write, so the staging costs one memory round trip.
 template <int THREADS>
-__device__ __forceinline__ void stage_twiddles(float2 *tw_lds, const float2 *__restrict__ tw, int K) {
-    for (int e = threadIdx.x; e < K; e += THREADS) tw_lds[e] = tw[e];
-}
+struct TwiddleStage {
+    float2 v[kEPT];
+    __device__ __forceinline__ void load(const float2 *__restrict__ tw, int K) {
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = threadIdx.x + u * THREADS;
+            if (e < K) v[u] = tw[e];
+        }
+    }
+    __device__ __forceinline__ void store(float2 *tw_lds, int K) const {
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = threadIdx.x + u * THREADS;
+            if (e < K) tw_lds[e] = v[u];
+        }
+    }
+};
+
 
 // Product of the scaling factors of the leading axes of image row r
 // (row-major over axes 0..d-2), 32-bit index arithmetic.
@@ -218,6 +250,31 @@ __device__ __forceinline__ float row_scale(int d, const int *Nax, const float *c
     }
     return sc;
 }
+
+// row_scale with its loads issued at load() and the product formed at value(),
+// so the loads overlap other work.
+struct RowScale {
+    float f[kMaxDim - 1];
+    int n;
+    __device__ __forceinline__ void load(int d, const int *Nax, const float *const *scale, int r) {
+        n = d - 1;
+#pragma unroll
+        for (int a = kMaxDim - 2; a >= 0; --a) {
+            if (a < n) {
+                const int i = r % Nax[a];
+                r /= Nax[a];
+                f[a] = scale[a][i];
+            }
+        }
+    }
+    __device__ __forceinline__ float value() const {
+        float sc = 1.0f;
+#pragma unroll
+        for (int a = kMaxDim - 2; a >= 0; --a)
+            if (a < n) sc *= f[a];
+        return sc;
+    }
+};
 
 // Grid position of image index i on an axis of image size N and grid size K
 // (n = i - N/2 wrapped modulo K), and its inverse (-1 in the zero gap).
@@ -233,51 +290,94 @@ __device__ __forceinline__ int src_row(int q, int N, int K) {
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lines_per_wg) {
     extern __shared__ float2 lds[];
-    __shared__ float rsc[kMaxLinesPerWg];
-    __shared__ int xbase[kMaxLinesPerWg];
-    __shared__ int cbase[kMaxLinesPerWg];
     const int K = a.K, N = a.N;
     float2 *tw = lds;
     float2 *s = lds + K;
     const int64_t total = int64_t(a.B) * a.C * a.rows;
     const int64_t l0 = int64_t(blockIdx.x) * lines_per_wg;
-    const int nl = int(min(int64_t(lines_per_wg), total - l0));
-    stage_twiddles<THREADS>(tw, a.tw, K);
-    if (threadIdx.x < nl) {
-        const int64_t l = l0 + threadIdx.x;
+    const int nl = int(min(int64_t(lines_per_wg), total - l0));  // 1..64
+    // Line `lane` of the workgroup, known to that lane of every wavefront: the
+    // image and coil row offsets and the product of the leading axes' scaling
+    // factors (applied after the FFT, which is linear along the line).
+    const int lane = threadIdx.x & 63;
+    int xb = 0, cb = 0;
+    RowScale rsf;
+    {
+        const int64_t l = l0 + min(lane, nl - 1);
         const int g = int(l / a.rows);
         const int r = int(l - int64_t(g) * a.rows);
         const int b = g / a.C;
         const int c = g - b * a.C;
-        rsc[threadIdx.x] = row_scale(a.d, a.Nax, a.scale, r);
-        xbase[threadIdx.x] = (b * int(a.rows) + r) * N;
-        cbase[threadIdx.x] = (c * int(a.rows) + r) * N;
+        rsf.load(a.d, a.Nax, a.scale, r);  // consumed after the FFT
+        xb = (b * int(a.rows) + r) * N;
+        cb = (c * int(a.rows) + r) * N;
     }
-    __syncthreads();
+    TwiddleStage<THREADS> tws;
+    tws.load(a.tw, K);
+    // the tile holds nl * K <= THREADS * kEPT elements: every load is issued
+    // before the first use
+    const int ne = nl * K;
+    const FastDiv byK(K);
     const float *slast = a.scale[a.d - 1];
-    for (int e = threadIdx.x; e < nl * K; e += THREADS) {
-        const int lw = e / K, q = e - lw * K;
-        float2 v = make_float2(0.f, 0.f);
-        const int i = src_row(q, N, K);
-        if (i >= 0) {
-            v = cscale(a.x[xbase[lw] + i], rsc[lw] * slast[i]);
-            if (a.coils) v = cmul(v, a.coils[cbase[lw] + i]);
-        }
-        s[e] = v;
+    // (loads land in registers without a default value, so no copy waits for
+    // them; `live` marks the elements that read the image)
+    // (branch-free: indices are clamped into the row and `live` marks the
+    // elements that really read the image, so no load waits on another)
+    float2 xv[kEPT], cv[kEPT];
+    float sv[kEPT];
+    unsigned live = 0;
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = min(int(threadIdx.x) + u * THREADS, ne - 1);
+        const int lw = byK.div(e);
+        const int i = src_row(byK.rem(e, lw), N, K);
+        live |= (int(threadIdx.x) + u * THREADS < ne && i >= 0) ? 1u << u : 0u;
+        const int ic = max(i, 0);
+        // one grid per image row without coils: line l reads image row l
+        const int xbl = a.C == 1 ? int(l0 + lw) * N : __shfl(xb, lw);
+        xv[u] = a.x[xbl + ic];
+        sv[u] = slast[ic];
+        if (a.coils) cv[u] = a.coils[__shfl(cb, lw) + ic];
+    }
+    // values first, without branches (one wait for all loads), then the writes
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        float2 v = cscale(xv[u], sv[u]);
+        if (a.coils) v = cmul(v, cv[u]);
+        xv[u] = (live & (1u << u)) ? v : make_float2(0.f, 0.f);
+    }
+    tws.store(tw, K);
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = threadIdx.x + u * THREADS;
+        if (e < ne) s[e] = xv[u];
     }
     __syncthreads();
     lds_fft<THREADS, false, false>(s, nl, K, K, 1, a.rp, tw);
+    const float rs = rsf.value();
     float2 *out = a.out + l0 * K;
-    if (a.mult || a.phase) {
-        for (int e = threadIdx.x; e < nl * K; e += THREADS) {
-            const int lw = e / K, q = e - lw * K;
-            float2 v = s[e];
-            if (a.phase) v = cmul(v, a.phase[q]);
-            if (a.mult) v = cmul(v, a.mult[((l0 + lw) % a.rows) * K + q]);
-            out[e] = v;
-        }
-    } else {
-        for (int e = threadIdx.x; e < nl * K; e += THREADS) out[e] = s[e];
+    float2 pv[kEPT], mv[kEPT];
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = min(int(threadIdx.x) + u * THREADS, ne - 1);
+        const int lw = byK.div(e);
+        const int q = byK.rem(e, lw);
+        if (a.phase) pv[u] = a.phase[q];
+        if (a.mult) mv[u] = a.mult[((l0 + lw) % a.rows) * K + q];
+    }
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = min(int(threadIdx.x) + u * THREADS, ne - 1);
+        float2 v = s[e];
+        if (a.d > 1) v = cscale(v, __shfl(rs, byK.div(e)));  // row scale of the element's line
+        if (a.phase) v = cmul(v, pv[u]);
+        if (a.mult) v = cmul(v, mv[u]);
+        pv[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = threadIdx.x + u * THREADS;
+        if (e < ne) out[e] = pv[u];
     }
 }
 
@@ -296,33 +396,68 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
     const int wv = int(min(int64_t(W), a.inner - c0));
     const float2 *in = a.in + ((g * a.outer + o) * a.Lin) * a.inner + c0;
     float2 *out = a.out + ((g * a.outer + o) * a.Lout) * a.inner + c0;
-    stage_twiddles<THREADS>(tw, a.tw, K);
-    for (int e = threadIdx.x; e < K * W; e += THREADS) {
-        const int q = e / W, w = e - q * W;
-        float2 v = make_float2(0.f, 0.f);
-        if (w < wv) {
+    TwiddleStage<THREADS> tws;
+    tws.load(a.tw, K);
+    // the tile holds K * W <= THREADS * kEPT elements
+    const int ne = K * W;
+    const FastDiv byW(W);
+    if (!a.hot_of_tile) {
+        // every load is issued before the first use
+        // (no default values in the load registers, so no copy waits for a
+        // load; `live` marks the elements that read the input)
+        float2 v[kEPT], mv[kEPT], pv[kEPT];
+        unsigned live = 0;
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = threadIdx.x + u * THREADS;
+            const int q = byW.div(min(e, ne - 1));
+            const int w = e - __umul24(q, W);
             // forward: grid row q takes image row src_row (zero rows when Lin < K,
             // the centring shift when Lin == K); inverse: the input is the grid
             const int i = INV ? q : src_row(q, a.Lin, K);
-            if (i >= 0) {
-                int hot = -1;
-                int cell = 0;
-                if (a.hot_of_tile) {
-                    // axis 0 row q, column c0 + w over the remaining axes
-                    int64_t c = c0 + w;
-                    int tile = 0;
-                    int kk[kMaxDim];
-                    kk[0] = q;
-                    for (int ax = a.d - 1; ax >= 1; --ax) {
-                        kk[ax] = int(c % a.Kax[ax]);
-                        c /= a.Kax[ax];
-                    }
-                    for (int ax = 0; ax < a.d; ++ax) {
-                        tile = tile * a.nt[ax] + kk[ax] / a.T[ax];
-                        cell = cell * a.T[ax] + kk[ax] % a.T[ax];
-                    }
-                    hot = a.hot_of_tile[tile];
+            if (e < ne && w < wv && i >= 0) {
+                live |= 1u << u;
+                v[u] = in[int64_t(i) * a.inner + w];
+                if (a.mult) mv[u] = a.mult[(o * a.Lin + i) * a.inner + c0 + w];
+                if (INV && a.phase) pv[u] = a.phase[q];
+            }
+        }
+        // values first, without branches (one wait for all loads), then the writes
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            float2 x = v[u];
+            if (a.mult) x = cmul(x, mv[u]);
+            if (INV && a.phase) x = cmulcj(pv[u], x);
+            v[u] = (live & (1u << u)) ? x : make_float2(0.f, 0.f);
+        }
+        tws.store(tw, K);
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = threadIdx.x + u * THREADS;
+            if (e < ne) s[e] = v[u];
+        }
+    } else {
+        tws.store(tw, K);
+        for (int e = threadIdx.x; e < ne; e += THREADS) {
+            const int q = e / W, w = e - q * W;
+            float2 v = make_float2(0.f, 0.f);
+            const int i = INV ? q : src_row(q, a.Lin, K);
+            if (w < wv && i >= 0) {
+                // axis 0 row q, column c0 + w over the remaining axes; cells of
+                // split tiles are the sum of their partial tiles
+                int64_t c = c0 + w;
+                int tile = 0, cell = 0;
+                int kk[kMaxDim];
+                kk[0] = q;
+                for (int ax = a.d - 1; ax >= 1; --ax) {
+                    kk[ax] = int(c % a.Kax[ax]);
+                    c /= a.Kax[ax];
                 }
+                for (int ax = 0; ax < a.d; ++ax) {
+                    tile = tile * a.nt[ax] + kk[ax] / a.T[ax];
+                    cell = cell * a.T[ax] + kk[ax] % a.T[ax];
+                }
+                const int hot = a.hot_of_tile[tile];
                 if (hot < 0) {
                     v = in[int64_t(i) * a.inner + w];
                     if (a.mult) v = cmul(v, a.mult[(o * a.Lin + i) * a.inner + c0 + w]);
@@ -333,19 +468,37 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
                 }
                 if (INV && a.phase) v = cmulcj(a.phase[q], v);
             }
+            s[e] = v;
         }
-        s[e] = v;
     }
     __syncthreads();
     lds_fft<THREADS, INV, true>(s, W, K, 1, W, a.rp, tw);
-    for (int e = threadIdx.x; e < a.Lout * W; e += THREADS) {
-        const int i = e / W, w = e - i * W;
-        if (w < wv) {
-            const int q = INV ? pad_pos(i, a.Lout, K) : i;
-            float2 v = s[q * W + w];
-            if (!INV && a.phase) v = cmul(v, a.phase[q]);
-            out[int64_t(i) * a.inner + w] = v;
+    // Lout * W <= K * W outputs
+    const int no = a.Lout * W;
+    float2 pv[kEPT];
+    if (!INV && a.phase) {
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = min(int(threadIdx.x) + u * THREADS, no - 1);
+            pv[u] = a.phase[byW.div(e)];
         }
+    }
+    // values first, without branches, then the writes
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = min(int(threadIdx.x) + u * THREADS, no - 1);
+        const int i = byW.div(e);
+        const int q = INV ? pad_pos(i, a.Lout, K) : i;
+        float2 v = s[__umul24(q, W) + byW.rem(e, i)];
+        if (!INV && a.phase) v = cmul(v, pv[u]);
+        pv[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = threadIdx.x + u * THREADS;
+        const int i = byW.div(min(e, no - 1));
+        const int w = e - __umul24(i, W);
+        if (e < no && w < wv) out[int64_t(i) * a.inner + w] = pv[u];
     }
 }
 
@@ -356,18 +509,84 @@ __global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_
     const int K = a.K, N = a.N, C = a.C;
     float2 *tw = lds;
     float2 *s = lds + K;
-    // output accumulators (rows_per_wg * N of them) after the tile
-    float2 *acc = s + rows_per_wg * coils_per_round * K;
     const int64_t nrt = (a.rows + rows_per_wg - 1) / rows_per_wg;
     const int64_t b = blockIdx.x / nrt;
     const int64_t r0 = (blockIdx.x % nrt) * rows_per_wg;
     const int nr = int(min(int64_t(rows_per_wg), a.rows - r0));
-    stage_twiddles<THREADS>(tw, a.tw, K);
-    if (threadIdx.x < nr) rsc[threadIdx.x] = row_scale(a.d, a.Nax, a.scale, int(r0) + threadIdx.x);
-    const bool one_round = coils_per_round >= C;
-    if (!one_round)
-        for (int e = threadIdx.x; e < nr * N; e += THREADS) acc[e] = make_float2(0.f, 0.f);
+    TwiddleStage<THREADS> tws;
+    tws.load(a.tw, K);
     const float *slast = a.scale[a.d - 1];
+    if (coils_per_round >= C) {
+        const FastDiv byK(K), byN(N), byC(C);
+        // all coils of the rows in one tile (nr * C * K <= THREADS * kEPT
+        // elements, nr * N outputs): every load is issued before the first use.
+        // Lane rr (< nr <= 64) of every wavefront holds row rr's scaling factor.
+        RowScale rsf;
+        rsf.load(a.d, a.Nax, a.scale, int(r0) + min(int(threadIdx.x & 63), nr - 1));
+        const int nl = nr * C;
+        const int ne = nl * K;
+        float2 v[kEPT], pv[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = min(int(threadIdx.x) + u * THREADS, ne - 1);  // (clamped: every load is in bounds)
+            const int lw = byK.div(e);
+            const int q = byK.rem(e, lw);
+            const int rr = byC.div(lw), cc = byC.rem(lw, rr);
+            v[u] = a.in[((b * C + cc) * a.rows + r0 + rr) * K + q];
+            if (a.phase) pv[u] = a.phase[q];
+        }
+        if (a.phase) {
+#pragma unroll
+            for (int u = 0; u < kEPT; ++u) v[u] = cmulcj(pv[u], v[u]);
+        }
+        tws.store(tw, K);
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = threadIdx.x + u * THREADS;
+            if (e < ne) s[e] = v[u];
+        }
+        __syncthreads();
+        lds_fft<THREADS, true, false>(s, nl, K, K, 1, a.rp, tw);
+        const float rs = rsf.value();
+        const int no = nr * N;
+        float sv[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = min(int(threadIdx.x) + u * THREADS, no - 1);
+            sv[u] = slast[byN.rem(e, byN.div(e))];
+        }
+        // values first (one wait for the scaling-factor loads), then the writes
+        float2 res[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = min(int(threadIdx.x) + u * THREADS, no - 1);
+            const int rr = byN.div(e), i = byN.rem(e, rr);
+            const int q = pad_pos(i, N, K);
+            float2 sum = make_float2(0.f, 0.f);
+            if (a.coils) {
+#pragma unroll 1
+                for (int cc = 0; cc < C; ++cc)
+                    sum = cadd(sum, cmulcj(a.coils[(int64_t(cc) * a.rows + r0 + rr) * N + i], s[(rr * C + cc) * K + q]));
+            } else {
+#pragma unroll 1
+                for (int cc = 0; cc < C; ++cc) sum = cadd(sum, s[(rr * C + cc) * K + q]);
+            }
+            res[u] = cscale(sum, __shfl(rs, rr) * sv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = threadIdx.x + u * THREADS;
+            const int rr = byN.div(min(e, no - 1)), i = e - __umul24(rr, N);
+            if (e < no) a.x[(b * a.rows + r0 + rr) * N + i] = res[u];
+        }
+        return;
+    }
+    // more coils than one tile holds (C * K > the tile): rounds of
+    // coils_per_round coils summed in LDS accumulators after the tile
+    tws.store(tw, K);
+    if (threadIdx.x < nr) rsc[threadIdx.x] = row_scale(a.d, a.Nax, a.scale, int(r0) + threadIdx.x);
+    float2 *acc = s + rows_per_wg * coils_per_round * K;
+    for (int e = threadIdx.x; e < nr * N; e += THREADS) acc[e] = make_float2(0.f, 0.f);
     for (int c0 = 0; c0 < C; c0 += coils_per_round) {
         const int nc = min(coils_per_round, C - c0);
         const int nl = nr * nc;
@@ -383,25 +602,19 @@ __global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_
         for (int e = threadIdx.x; e < nr * N; e += THREADS) {
             const int rr = e / N, i = e - rr * N;
             const int q = pad_pos(i, N, K);
-            float2 v = make_float2(0.f, 0.f);
+            float2 sum = make_float2(0.f, 0.f);
             for (int cc = 0; cc < nc; ++cc) {
                 float2 t = s[(rr * nc + cc) * K + q];
                 if (a.coils) t = cmulcj(a.coils[(int64_t(c0 + cc) * a.rows + r0 + rr) * N + i], t);
-                v = cadd(v, t);
+                sum = cadd(sum, t);
             }
-            if (one_round) {
-                a.x[(b * a.rows + r0 + rr) * N + i] = cscale(v, rsc[rr] * slast[i]);
-            } else {
-                acc[e] = cadd(acc[e], v);
-            }
+            acc[e] = cadd(acc[e], sum);
         }
         __syncthreads();
     }
-    if (!one_round) {
-        for (int e = threadIdx.x; e < nr * N; e += THREADS) {
-            const int rr = e / N, i = e - rr * N;
-            a.x[(b * a.rows + r0 + rr) * N + i] = cscale(acc[e], rsc[rr] * slast[i]);
-        }
+    for (int e = threadIdx.x; e < nr * N; e += THREADS) {
+        const int rr = e / N, i = e - rr * N;
+        a.x[(b * a.rows + r0 + rr) * N + i] = cscale(acc[e], rsc[rr] * slast[i]);
     }
 }
 

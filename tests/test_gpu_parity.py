@@ -312,6 +312,30 @@ def test_tuning_options_keep_parity(orc, dev, N, opts):
         assert rel_l2(_np(p.stage_vh(_t(yin, dev))), orc.grid(yin, om, N, K, 6)) < TOL
 
 
+@pytest.mark.parametrize("N,opts", [((64, 64), dict(tile=(16, 16), grid_chunk=64)),
+                                    ((64, 64), dict(tile=(16, 32), grid_chunk=64, grid_mfma=2)),
+                                    ((16, 16, 16), dict(tile=(8, 8, 16), grid_chunk=64))],
+                         ids=["2d_mfma", "2d_valu", "3d_mfma"])
+def test_split_tile_sums_agree_bitwise(dev, N, opts):
+    """The partial tiles of split gridding tiles are summed either by the first
+    inverse FFT pass or by a kernel of their own; both add the same numbers in
+    the same chunk order, so the adjoints agree bit for bit, single and
+    batched (per-grid partial slots)."""
+    from paper_1710_03197_amd import Plan
+    K = tuple(2 * n for n in N)
+    om = data.radial_2d(48, 128) if len(N) == 2 else data.koosh_ball_3d(96, 32)
+    y = _t(np.stack([_rand_c((om.shape[0],), 80 + b) for b in range(3)]), dev)
+    out = {}
+    for mode in (1, 2):
+        with Plan(_t(om, dev), N, K, 6, options=dict(opts, fuse_reduce=mode)) as p:
+            info = p.info()
+            assert info["n_items"] > int(np.prod([k // t for k, t in zip(K, info["tile"])]))  # some tiles split
+            out[mode] = (_np(p.adjoint(y[0])), _np(p.adjoint_batched(y)))
+    assert np.array_equal(out[1][0].view(np.uint32), out[2][0].view(np.uint32))
+    assert np.array_equal(out[1][1].view(np.uint32), out[2][1].view(np.uint32))
+    assert np.array_equal(out[2][1][0].view(np.uint32), out[2][0].view(np.uint32))
+
+
 @pytest.mark.parametrize("N,K", [((16, 16), (16, 32)), ((8, 12, 8), (8, 24, 16))])
 def test_axis_without_oversampling_matches_oracle(orc, dev, N, K):
     """K_a = N_a on a leading axis: the strided FFT passes must still centre
