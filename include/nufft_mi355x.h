@@ -93,7 +93,7 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *                 0: the default (1 for d = 3, 2 otherwise)
  *   fuse_reduce   1: the partial tiles of split gridding tiles are summed by
  *                 the first inverse FFT pass; 2: by a kernel of their own;
- *                 0: the default (1 for d = 3, 2 otherwise; always 2 for d = 1)
+ *                 0: the default (1 for d = 2, 2 otherwise; always 2 for d = 1)
  *   grid_mfma     1: gridding on the matrix cores (needs tile[d-1] = 16,
  *                 16, 32 or 64 cells over the leading axes and a tile
  *                 perimeter sum(tile) <= 61, else NUFFT_ERR_UNSUPPORTED);

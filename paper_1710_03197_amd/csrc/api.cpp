@@ -128,7 +128,7 @@ struct nufft_plan_s {
     int group_lanes = 64;
     int stage_floats = 0;
     HotTile *hot = nullptr;
-    int *hot_of_tile = nullptr;  // [nbins]: index into hot, or -1
+    int2 *split_of_tile = nullptr;  // [nbins]: (first partial slot, chunks), chunks 0 if not split
     int64_t n_hot = 0;
     int64_t n_slots = 0;
     // coils
@@ -237,7 +237,7 @@ void free_plan(nufft_plan_s *p) {
     dfree(p->items);
     dfree(p->iitems);
     dfree(p->hot);
-    dfree(p->hot_of_tile);
+    dfree(p->split_of_tile);
     dfree(p->coils);
     dfree(p->grid);
     dfree(p->tmp);
@@ -384,15 +384,15 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         std::stable_sort(iitems.begin(), iitems.end(),
                          [](const InterpItem &x, const InterpItem &y) { return x.count > y.count; });
     }
-    std::vector<int> hot_of_tile(size_t(p->nbins), -1);
-    for (size_t q = 0; q < hot.size(); ++q) hot_of_tile[size_t(hot[q].tile)] = int(q);
+    std::vector<int2> split_of_tile(size_t(p->nbins), make_int2(0, 0));
+    for (const HotTile &h : hot) split_of_tile[size_t(h.tile)] = make_int2(h.slot, h.nchunks);
     dfree(p->sub_start);
     dfree(p->items);
     dfree(p->iitems);
     dfree(p->hot);
-    dfree(p->hot_of_tile);
+    dfree(p->split_of_tile);
     HIP_TRY(upload(&p->sub_start, start), "upload bin offsets");
-    HIP_TRY(upload(&p->hot_of_tile, hot_of_tile), "upload split-tile index");
+    HIP_TRY(upload(&p->split_of_tile, split_of_tile), "upload split-tile index");
     HIP_TRY(upload(&p->items, items), "upload gridding work items");
     HIP_TRY(upload(&p->hot, hot), "upload split tiles");
     p->n_items = int64_t(items.size());
@@ -578,8 +578,8 @@ int run_shfh(nufft_plan_s *p, const FftGeom &f, const float2 *h, int B, float2 *
             a.phase = f.phase ? f.phase[ax] : nullptr;
             if (ax == 0) a.mult = mult;
             if (ax == 0 && fused_partials && p->n_hot > 0) {
-                a.hot_of_tile = p->hot_of_tile;
-                a.hot = p->hot;
+                if (mult) return fail(NUFFT_ERR_UNSUPPORTED, "split tiles and a Toeplitz product in one pass");
+                a.split_of_tile = p->split_of_tile;
                 a.partials = p->partials;
                 a.n_slots = p->n_slots;
                 a.tile_cells = p->tile_cells;
@@ -1142,7 +1142,12 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     // Defaults from measurement: in 3D the gridding's dependent loads through
     // the permutation cost more than one permute launch; in 2D they do not.
     p->presort = (opt && opt->presort) ? opt->presort == 1 : d == 3;
-    p->fuse_reduce = d >= 2 && ((opt && opt->fuse_reduce) ? opt->fuse_reduce == 1 : d == 3);
+    // Default from measurement: fused in 2D (saves a launch on a latency-bound
+    // problem), apart in 3D (the fused pass's extra registers cost occupancy).
+    p->fuse_reduce = d >= 2 && ((opt && opt->fuse_reduce) ? opt->fuse_reduce == 1 : d == 2);
+    // the fused pass divides column indices c < K_1 K_2 by K_2 with a 32-bit
+    // high multiply, exact while K_1 K_2^2 < 2^32
+    if (d == 3 && double(K[1]) * double(K[2]) * double(K[2]) >= 4294967296.0) p->fuse_reduce = false;
     // intermediate sizes of the FFT passes that land in the tmp buffer
     p->tmp_elems = 1;
     for (int pass = 0; pass < d - 1; ++pass) {

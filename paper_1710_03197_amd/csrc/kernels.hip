@@ -114,10 +114,12 @@ __device__ __forceinline__ void dft<8>(float2 *v) {
     v[7] = csub(e[3], o3);
 }
 
-// floor(e / D) for 0 <= e < 2^16 by a divisor 1 <= D < 2^16 fixed per launch:
-// q = floor(e m / 2^32) with m = ceil(2^32 / D) is exact because e D < 2^32
-// keeps the error e (m D - 2^32) / (D 2^32) below 1/D.  One high multiply
-// instead of an integer division.
+// floor(e / D) for a divisor D >= 1 fixed per launch: q = floor(e m / 2^32)
+// with m = ceil(2^32 / D) is exact whenever e (D - 1) < 2^32, since the error
+// e (m D - 2^32) / (D 2^32) then stays below 1/D.  One high multiply instead
+// of an integer division.  Every use here divides tile positions (< 4096) by
+// at most 4096, or a column index c < K_1 K_2 by K_2 with K_1 K_2^2 < 2^32
+// (checked when the plan is made).
 struct FastDiv {
     unsigned m;
     int d;
@@ -381,7 +383,10 @@ __global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lin
     }
 }
 
-template <int THREADS, bool INV>
+// SPLIT (inverse only): the first inverse pass of an adjoint whose split
+// gridding tiles are still partial tiles (its own instantiation, so the
+// common passes keep their register budget).
+template <int THREADS, bool INV, bool SPLIT>
 __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int W, int64_t ntc) {
     extern __shared__ float2 lds[];
     const int K = a.K;
@@ -401,12 +406,11 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
     // the tile holds K * W <= THREADS * kEPT elements
     const int ne = K * W;
     const FastDiv byW(W);
-    if (!a.hot_of_tile) {
-        // every load is issued before the first use
-        // (no default values in the load registers, so no copy waits for a
-        // load; `live` marks the elements that read the input)
-        float2 v[kEPT], mv[kEPT], pv[kEPT];
-        unsigned live = 0;
+    // (no default values in the load registers, so no copy waits for a load;
+    // `live` marks the elements that read the input)
+    float2 v[kEPT], mv[kEPT], pv[kEPT];
+    unsigned live = 0;
+    if constexpr (!SPLIT) {
 #pragma unroll
         for (int u = 0; u < kEPT; ++u) {
             const int e = threadIdx.x + u * THREADS;
@@ -422,60 +426,80 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
                 if (INV && a.phase) pv[u] = a.phase[q];
             }
         }
-        // values first, without branches (one wait for all loads), then the writes
-#pragma unroll
-        for (int u = 0; u < kEPT; ++u) {
-            float2 x = v[u];
-            if (a.mult) x = cmul(x, mv[u]);
-            if (INV && a.phase) x = cmulcj(pv[u], x);
-            v[u] = (live & (1u << u)) ? x : make_float2(0.f, 0.f);
-        }
-        tws.store(tw, K);
-#pragma unroll
-        for (int u = 0; u < kEPT; ++u) {
-            const int e = threadIdx.x + u * THREADS;
-            if (e < ne) s[e] = v[u];
-        }
     } else {
-        tws.store(tw, K);
-        for (int e = threadIdx.x; e < ne; e += THREADS) {
-            const int q = e / W, w = e - q * W;
-            float2 v = make_float2(0.f, 0.f);
-            const int i = INV ? q : src_row(q, a.Lin, K);
-            if (w < wv && i >= 0) {
-                // axis 0 row q, column c0 + w over the remaining axes; cells of
-                // split tiles are the sum of their partial tiles
-                int64_t c = c0 + w;
-                int tile = 0, cell = 0;
-                int kk[kMaxDim];
-                kk[0] = q;
-                for (int ax = a.d - 1; ax >= 1; --ax) {
-                    kk[ax] = int(c % a.Kax[ax]);
-                    c /= a.Kax[ax];
-                }
-                for (int ax = 0; ax < a.d; ++ax) {
-                    tile = tile * a.nt[ax] + kk[ax] / a.T[ax];
-                    cell = cell * a.T[ax] + kk[ax] % a.T[ax];
-                }
-                const int hot = a.hot_of_tile[tile];
-                if (hot < 0) {
-                    v = in[int64_t(i) * a.inner + w];
-                    if (a.mult) v = cmul(v, a.mult[(o * a.Lin + i) * a.inner + c0 + w]);
-                } else {
-                    const HotTile ht = a.hot[hot];
-                    const float2 *pp = a.partials + (g * a.n_slots + ht.slot) * a.tile_cells + cell;
-                    for (int k = 0; k < ht.nchunks; ++k) v = cadd(v, pp[int64_t(k) * a.tile_cells]);
-                }
-                if (INV && a.phase) v = cmulcj(a.phase[q], v);
+        // First inverse pass of the adjoint: a cell of a split gridding tile is
+        // the sum of its partial tiles in chunk order (the order, hence the bits,
+        // of k_reduce_partials).  Grid row q on axis 0, column c0 + w over the
+        // remaining axes; the input and the cell's split entry are loaded
+        // together, the partial tiles after that.
+        const FastDiv byT0(a.T[0]), byT1(a.T[1]), byT2(a.d > 2 ? a.T[2] : 1), byK2(a.d > 2 ? a.Kax[2] : 1);
+        int2 sp[kEPT];
+        int cellv[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int e = min(int(threadIdx.x) + u * THREADS, ne - 1);
+            const int q = byW.div(e);
+            const int w = min(e - __umul24(q, W), wv - 1);
+            const int i = INV ? q : max(src_row(q, a.Lin, K), 0);
+            live |= (int(threadIdx.x) + u * THREADS < ne && e - __umul24(q, W) < wv &&
+                     (INV || src_row(q, a.Lin, K) >= 0)) ? 1u << u : 0u;
+            // grid coordinates of the cell: k0 = q, then the column's axes
+            const int c = int(c0) + w;
+            int k1 = c, k2 = 0;
+            if (a.d > 2) {
+                k1 = byK2.div(c);
+                k2 = byK2.rem(c, k1);
             }
-            s[e] = v;
+            const int t0 = byT0.div(q), t1 = byT1.div(k1);
+            int tile = t0 * a.nt[1] + t1;
+            int cell = byT0.rem(q, t0) * a.T[1] + byT1.rem(k1, t1);
+            if (a.d > 2) {
+                const int t2 = byT2.div(k2);
+                tile = tile * a.nt[2] + t2;
+                cell = cell * a.T[2] + byT2.rem(k2, t2);
+            }
+            v[u] = in[int64_t(i) * a.inner + w];
+            sp[u] = a.split_of_tile[tile];
+            cellv[u] = cell;
+            if (INV && a.phase) pv[u] = a.phase[q];  // (never with a Toeplitz product)
         }
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+            const int n = sp[u].y;
+            if (n > 0) {
+                const float2 *pp = a.partials + (g * a.n_slots + sp[u].x) * a.tile_cells + cellv[u];
+                float2 acc = make_float2(0.f, 0.f);
+                for (int k0 = 0; k0 < n; k0 += 4) {
+                    float2 t[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k0 + j < n) t[j] = pp[int64_t(k0 + j) * a.tile_cells];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k0 + j < n) acc = cadd(acc, t[j]);
+                }
+                v[u] = acc;
+            }
+        }
+    }
+    // values first, without branches (one wait for all loads), then the writes
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        float2 x = v[u];
+        if (!SPLIT && a.mult) x = cmul(x, mv[u]);
+        if (INV && a.phase) x = cmulcj(pv[u], x);
+        v[u] = (live & (1u << u)) ? x : make_float2(0.f, 0.f);
+    }
+    tws.store(tw, K);
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+        const int e = threadIdx.x + u * THREADS;
+        if (e < ne) s[e] = v[u];
     }
     __syncthreads();
     lds_fft<THREADS, INV, true>(s, W, K, 1, W, a.rp, tw);
     // Lout * W <= K * W outputs
     const int no = a.Lout * W;
-    float2 pv[kEPT];
     if (!INV && a.phase) {
 #pragma unroll
         for (int u = 0; u < kEPT; ++u) {
@@ -489,16 +513,16 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
         const int e = min(int(threadIdx.x) + u * THREADS, no - 1);
         const int i = byW.div(e);
         const int q = INV ? pad_pos(i, a.Lout, K) : i;
-        float2 v = s[__umul24(q, W) + byW.rem(e, i)];
-        if (!INV && a.phase) v = cmul(v, pv[u]);
-        pv[u] = v;
+        float2 x = s[__umul24(q, W) + byW.rem(e, i)];
+        if (!INV && a.phase) x = cmul(x, pv[u]);
+        v[u] = x;
     }
 #pragma unroll
     for (int u = 0; u < kEPT; ++u) {
         const int e = threadIdx.x + u * THREADS;
         const int i = byW.div(min(e, no - 1));
         const int w = e - __umul24(i, W);
-        if (e < no && w < wv) out[int64_t(i) * a.inner + w] = pv[u];
+        if (e < no && w < wv) out[int64_t(i) * a.inner + w] = v[u];
     }
 }
 
@@ -1693,7 +1717,7 @@ struct FirstGo {
 template <int T>
 struct StridedGoF {
     static hipError_t go(const StridedPassArgs &a, hipStream_t s, int W, int64_t ntc, size_t lds, unsigned blocks) {
-        hipLaunchKernelGGL((k_strided_pass<T, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+        hipLaunchKernelGGL((k_strided_pass<T, false, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
         return hipGetLastError();
     }
 };
@@ -1701,7 +1725,10 @@ struct StridedGoF {
 template <int T>
 struct StridedGoI {
     static hipError_t go(const StridedPassArgs &a, hipStream_t s, int W, int64_t ntc, size_t lds, unsigned blocks) {
-        hipLaunchKernelGGL((k_strided_pass<T, true>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+        if (a.split_of_tile)
+            hipLaunchKernelGGL((k_strided_pass<T, true, true>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+        else
+            hipLaunchKernelGGL((k_strided_pass<T, true, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
         return hipGetLastError();
     }
 };

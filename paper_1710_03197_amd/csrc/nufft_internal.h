@@ -107,11 +107,10 @@ struct StridedPassArgs {
     bool inverse;
     const float2 *mult;  // inverse pass: the input times mult (same layout, shared by all grids)
     int target_groups;
-    // First inverse pass of the adjoint only (hot_of_tile != nullptr): cells of
+    // First inverse pass of the adjoint only (split_of_tile != nullptr): cells of
     // split gridding tiles are read as the sum of their partial tiles.
-    const int *hot_of_tile;  // [tiles] index into hot, or -1
-    const HotTile *hot;
-    const float2 *partials;  // [grids][n_slots][tile_cells]
+    const int2 *split_of_tile;  // [tiles] (first partial slot, chunks); chunks 0: not split
+    const float2 *partials;     // [grids][n_slots][tile_cells]
     int64_t n_slots;
     int tile_cells;
     int d;
