@@ -643,6 +643,19 @@ __global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_
 }
 
 // ------------------------------------------------------------ interpolation window
+// k0 mod K for an integer-valued k0 (|k0| <= 1e15, checked when the plan is
+// made).  Trajectories inside [-pi, pi) give |k0| <= K/2 + J/2 < K, handled
+// without the 64-bit division the general case needs.
+__device__ __forceinline__ int wrap_first_tap(double k0, int K) {
+    const double Kd = double(K);
+    if (k0 >= 0.0 && k0 < Kd) return int(k0);
+    if (k0 < 0.0 && k0 >= -Kd) return int(k0) + K;
+    long long kw = static_cast<long long>(k0) % K;
+    if (kw < 0) kw += K;
+    return int(kw);
+}
+
+
 // First tap k0 = floor(u - J/2) + 1 with u = omega * K/(2 pi) in float64, the
 // J wrapped grid indices and the offset f = u - k0 - (J/2 - 1) in [0, 1).
 template <int J>
@@ -651,11 +664,10 @@ __device__ __forceinline__ float window_pos(const SampleGeom &geo, int ax, float
     const double k0 = floor(u - 0.5 * J) + 1.0;
     const float f = float(u - k0 - (0.5 * J - 1.0));
     const int K = geo.K[ax];
-    long long kw = static_cast<long long>(k0) % K;
-    if (kw < 0) kw += K;
+    const int kw = wrap_first_tap(k0, K);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        int k = int(kw) + j;
+        int k = kw + j;
         kk[j] = k >= K ? k - K : k;
     }
     return f;
@@ -686,9 +698,7 @@ __device__ __forceinline__ int mm_wrap_from(const SampleGeom &geo, int ax, float
     const double u = __dmul_rn(double(om), geo.C[ax]);
     const double k0 = floor(u - 0.5 * geo.J) + 1.0;
     const int K = geo.K[ax];
-    long long kw = static_cast<long long>(k0) % K;
-    if (kw < 0) kw += K;
-    return K - int(kw);
+    return K - wrap_first_tap(k0, K);
 }
 
 template <int NJ>
@@ -1045,9 +1055,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
                 const double k0 = floor(u - 0.5 * J) + 1.0;
                 const float fr = float(u - k0 - (0.5 * J - 1.0));
                 const int K = a.geo.K[ax];
-                long long kw = static_cast<long long>(k0) % K;
-                if (kw < 0) kw += K;
-                int o = int(kw) - base[ax];
+                const int kw = wrap_first_tap(k0, K);
+                int o = kw - base[ax];
                 if (a.nt[ax] > 1 && o >= a.T[ax]) o -= K;  // window wrapping in from the top
                 const float z = 2.0f * fr - 1.0f;
                 float wv[JP];
@@ -1284,12 +1293,11 @@ __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
                 const double k0 = floor(u - 0.5 * J) + 1.0;
                 const float fr = float(u - k0 - (0.5 * J - 1.0));
                 const int K = a.geo.K[ax];
-                long long kw = static_cast<long long>(k0) % K;
-                if (kw < 0) kw += K;
-                const int o = int(kw) - base[ax];  // first tap relative to the tile, in [-base, K - base)
+                const int kw = wrap_first_tap(k0, K);
+                const int o = kw - base[ax];  // first tap relative to the tile, in [-base, K - base)
                 float wv[NJ];
                 poly_rows<NJ>(a.geo.coef[ax], a.geo.jp, a.geo.nq[ax], 2.0f * fr - 1.0f, wv);
-                if (a.geo.minmax) mm_sign_taps<NJ>(wv, K - int(kw));
+                if (a.geo.minmax) mm_sign_taps<NJ>(wv, K - kw);
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
                     if (j < J) {
