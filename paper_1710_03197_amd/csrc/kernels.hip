@@ -973,6 +973,19 @@ __device__ __forceinline__ int grid_item_segments(const GridArgs &a, const int *
     return a.n_kinds;
 }
 
+// Segment of item sample f (the last segment whose start is <= f) for a batch
+// of consecutive samples fb .. fb + span - 1.  `cursor` is uniform over the
+// batch's lanes and kept across the item's batches, which only move forward:
+// it is advanced to the batch's first sample, then every segment start inside
+// the batch adds one for the lanes at or past it.  The same segment as a scan
+// from segment 0, without a divergent per-lane loop.
+__device__ __forceinline__ int batch_segment(const int *seg_pre, int nseg, int &cursor, int fb, int span, int f) {
+    while (cursor + 1 < nseg && seg_pre[cursor + 1] <= fb) ++cursor;
+    int sg = cursor;
+    for (int k = cursor + 1; k < nseg && seg_pre[k] < fb + span; ++k) sg += seg_pre[k] <= f ? 1 : 0;
+    return sg;
+}
+
 template <int DIM, int LS, int JP>
 __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     extern __shared__ float4 stage_mem[];  // float4: 16-byte aligned rows for the vector reads
@@ -1038,13 +1051,13 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     // A group of one wavefront stages and consumes its own batches, so it
     // synchronises only with itself and runs ahead of the other groups.
     const int per_iter = B * ngroups;
+    int cursor = 0;
     for (int b0 = 0; b0 < n; b0 += per_iter) {
         // ---- stage one batch per group: lane `lane` stages sample b0 + grp*B + lane
         const int s_idx = b0 + grp * B + lane;
+        const int sg = batch_segment(seg_pre, nseg, cursor, f0 + b0 + grp * B, B, f0 + s_idx);
         if (s_idx < n) {
             const int f = f0 + s_idx;
-            int sg = 0;
-            while (sg + 1 < nseg && seg_pre[sg + 1] <= f) ++sg;
             const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
             float wl_row[JP];  // last-axis weights, spread on the row below
             int o_last = 0;
@@ -1262,13 +1275,13 @@ __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
     float pom[DIM];
     float2 pv = make_float2(0.f, 0.f);
     bool pvalid = false;
+    int cursor = 0;
     auto fetch = [&](int b) {
         const int s_idx = b + wave * 64 + lane;
         pvalid = s_idx < n;
+        const int sg = batch_segment(seg_pre, nseg, cursor, f0 + b + wave * 64, 64, f0 + s_idx);
         if (pvalid) {
             const int f = f0 + s_idx;
-            int sg = 0;
-            while (sg + 1 < nseg && seg_pre[sg + 1] <= f) ++sg;
             const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
 #pragma unroll
             for (int ax = 0; ax < DIM; ++ax) pom[ax] = a.om_sorted[i * DIM + ax];
