@@ -316,7 +316,16 @@ bool radix_plan(int K, RadixPlan *rp) {
             rem /= r;
         }
     }
-    return rem == 1;
+    if (rem != 1) return false;
+    auto magic = [](int D) { return D > 1 ? 0xFFFFFFFFu / unsigned(D) + 1u : 0u; };
+    int Ns = 1;
+    for (int p = 0; p < rp->n; ++p) {
+        rp->span[p] = K / (Ns * rp->r[p]);
+        rp->m_ns[p] = magic(Ns);
+        rp->m_nbl[p] = magic(K / rp->r[p]);
+        Ns *= rp->r[p];
+    }
+    return true;
 }
 
 }  // namespace nufft

@@ -124,6 +124,7 @@ struct FastDiv {
     unsigned m;
     int d;
     __device__ __forceinline__ explicit FastDiv(int D) : m(D > 1 ? 0xFFFFFFFFu / unsigned(D) + 1u : 0u), d(D) {}
+    __device__ __forceinline__ FastDiv(unsigned magic, int D) : m(magic), d(D) {}  // magic made on the host
     __device__ __forceinline__ int div(int e) const { return d > 1 ? int(__umulhi(unsigned(e), m)) : e; }
     __device__ __forceinline__ int rem(int e, int q) const { return e - __umul24(q, d); }
 };
@@ -138,12 +139,14 @@ struct FastDiv {
 constexpr int kEPT = 8;  // complex elements per thread
 
 template <int THREADS, int R, bool INV, bool STRIDED>
-__device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS, int ES, int Ns,
-                                           const float2 *tw) {
+__device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS, int ES, int Ns, int span,
+                                           unsigned m_ns, unsigned m_nbl, const float2 *tw) {
     constexpr int NB = (kEPT + R - 1) / R;
     const int nbl = K / R;
     const int total = nlines * nbl;
-    const FastDiv by_line(STRIDED ? nlines : nbl), by_ns(Ns);
+    // (the line count's magic is made per pass: kept across passes it costs
+    // the strided passes about 20 registers)
+    const FastDiv by_line = STRIDED ? FastDiv(nlines) : FastDiv(m_nbl, nbl), by_ns(m_ns, Ns);
     float2 v[NB][R];
     int lidx[NB], jidx[NB];
 #pragma unroll
@@ -168,7 +171,6 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
         }
     }
     __syncthreads();
-    const int span = K / (Ns * R);
 #pragma unroll
     for (int it = 0; it < NB; ++it) {
         const int b = threadIdx.x + it * THREADS;
@@ -206,12 +208,14 @@ __device__ void lds_fft(float2 *s, int nlines, int K, int LS, int ES, const Radi
     int Ns = 1;
     for (int p = 0; p < rp.n; ++p) {
         const int R = rp.r[p];
+        const int sp = rp.span[p];
+        const unsigned mn = rp.m_ns[p], mb = rp.m_nbl[p];
         switch (R) {
-            case 8: radix_pass<THREADS, 8, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 4: radix_pass<THREADS, 4, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 2: radix_pass<THREADS, 2, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 3: radix_pass<THREADS, 3, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
-            case 5: radix_pass<THREADS, 5, INV, STRIDED>(s, nlines, K, LS, ES, Ns, tw); break;
+            case 8: radix_pass<THREADS, 8, INV, STRIDED>(s, nlines, K, LS, ES, Ns, sp, mn, mb, tw); break;
+            case 4: radix_pass<THREADS, 4, INV, STRIDED>(s, nlines, K, LS, ES, Ns, sp, mn, mb, tw); break;
+            case 2: radix_pass<THREADS, 2, INV, STRIDED>(s, nlines, K, LS, ES, Ns, sp, mn, mb, tw); break;
+            case 3: radix_pass<THREADS, 3, INV, STRIDED>(s, nlines, K, LS, ES, Ns, sp, mn, mb, tw); break;
+            case 5: radix_pass<THREADS, 5, INV, STRIDED>(s, nlines, K, LS, ES, Ns, sp, mn, mb, tw); break;
             default: break;
         }
         Ns *= R;

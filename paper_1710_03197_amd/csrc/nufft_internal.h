@@ -22,9 +22,16 @@ constexpr int kInterpSamplesPerThread = 2;  // gather work item = 512 samples
 constexpr int kLdsBudget = 64 * 1024;      // bytes of LDS a gather or gridding tile may use
 
 // Radix schedule of one FFT axis (Stockham, product of r[] == K).
+// Per pass p (Ns = r[0] ... r[p-1] the length of the sub-transforms done so
+// far): span = K / (Ns r[p]), and the division magics ceil(2^32 / D) of
+// D = Ns and D = K / r[p] (0 for D = 1) the passes use instead of integer
+// divisions.
 struct RadixPlan {
     int n;
     int r[kMaxPasses];
+    int span[kMaxPasses];
+    unsigned m_ns[kMaxPasses];
+    unsigned m_nbl[kMaxPasses];
 };
 
 // Kaiser-Bessel kernel of one axis (unnormalised, phi(0) = I0(beta)) as per-tap
