@@ -945,33 +945,39 @@ __device__ __forceinline__ void group_sync(int gsize) {
 template <int DIM>
 __device__ __forceinline__ int grid_item_segments(const GridArgs &a, const int *tc, int *seg_lo, int *seg_hi,
                                                   int *seg_pre) {
-    if (threadIdx.x < a.n_kinds) {
-        const int kind = a.kinds[threadIdx.x];
-        int bin = 0;
+    // lane q < n_kinds (<= 27) of the first wavefront takes segment kind q; the
+    // offsets of the segments in the item's sample list are a wavefront scan
+    static_assert(kMaxNeighbors <= 64, "one wavefront holds every segment kind");
+    if (threadIdx.x < 64) {
+        const int q = threadIdx.x;
+        int lo = 0, hi = 0;
+        if (q < a.n_kinds) {
+            const int kind = a.kinds[q];
+            int bin = 0;
 #pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) {
-            int b = tc[ax] - ((kind >> ax) & 1);
-            if (b < 0) b += a.nt[ax];
-            bin = bin * a.nt[ax] + b;
+            for (int ax = 0; ax < DIM; ++ax) {
+                int b = tc[ax] - ((kind >> ax) & 1);
+                if (b < 0) b += a.nt[ax];
+                bin = bin * a.nt[ax] + b;
+            }
+            const int code = (kind >> 8) & 255;
+            const int base = bin << DIM;
+            lo = a.sub_start[code == 255 ? base : base + code];
+            hi = a.sub_start[code == 255 ? base + (1 << DIM) : base + code + 1];
         }
-        const int code = (kind >> 8) & 255;
-        const int base = bin << DIM;
-        if (code == 255) {
-            seg_lo[threadIdx.x] = a.sub_start[base];
-            seg_hi[threadIdx.x] = a.sub_start[base + (1 << DIM)];
-        } else {
-            seg_lo[threadIdx.x] = a.sub_start[base + code];
-            seg_hi[threadIdx.x] = a.sub_start[base + code + 1];
+        int incl = hi - lo;  // inclusive prefix of the segment lengths
+#pragma unroll
+        for (int d = 1; d < 32; d <<= 1) {
+            const int t = __shfl_up(incl, d);
+            if (q >= d) incl += t;
         }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int pre = 0;
-        for (int q = 0; q < a.n_kinds; ++q) {
-            seg_pre[q] = pre;
-            pre += seg_hi[q] - seg_lo[q];
+        if (q < a.n_kinds) {
+            seg_lo[q] = lo;
+            seg_hi[q] = hi;
+            seg_pre[q] = incl - (hi - lo);
+            if (q == a.n_kinds - 1) seg_pre[a.n_kinds] = incl;
         }
-        seg_pre[a.n_kinds] = pre;
+        if (a.n_kinds == 0 && q == 0) seg_pre[0] = 0;
     }
     __syncthreads();
     return a.n_kinds;
