@@ -129,6 +129,7 @@ struct nufft_plan_s {
     int stage_floats = 0;
     HotTile *hot = nullptr;
     int2 *split_of_tile = nullptr;  // [nbins]: (first partial slot, chunks), chunks 0 if not split
+    int2 *item_segs = nullptr;      // [n_items][kMaxNeighbors + 1]: (segment start, offset in the item's list)
     int64_t n_hot = 0;
     int64_t n_slots = 0;
     // coils
@@ -238,6 +239,7 @@ void free_plan(nufft_plan_s *p) {
     dfree(p->iitems);
     dfree(p->hot);
     dfree(p->split_of_tile);
+    dfree(p->item_segs);
     dfree(p->coils);
     dfree(p->grid);
     dfree(p->tmp);
@@ -386,12 +388,36 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
     }
     std::vector<int2> split_of_tile(size_t(p->nbins), make_int2(0, 0));
     for (const HotTile &h : hot) split_of_tile[size_t(h.tile)] = make_int2(h.slot, h.nchunks);
+    // The segments of every gridding item's tile, in the order tile_segments
+    // lists them: (first sorted sample, offset of the segment in the item's
+    // sample list), and (0, total) after the last, so a work item reads its
+    // table in the same round trip as the item itself.
+    constexpr int kSegRow = kMaxNeighbors + 1;
+    std::vector<int2> item_segs(std::max<size_t>(items.size(), 1) * kSegRow, make_int2(0, 0));
+    for (size_t q = 0; q < items.size(); ++q) {
+        int tc[kMaxDim];
+        int64_t rem = items[q].tile;
+        for (int a = d - 1; a >= 0; --a) {
+            tc[a] = int(rem % p->nt[a]);
+            rem /= p->nt[a];
+        }
+        int lo[kMaxNeighbors], hi[kMaxNeighbors];
+        const int nseg = tile_segments(d, tc, p->nt, p->R, start.data(), lo, hi);
+        int pre = 0;
+        for (int k = 0; k < nseg; ++k) {
+            item_segs[q * kSegRow + size_t(k)] = make_int2(lo[k], pre);
+            pre += hi[k] - lo[k];
+        }
+        item_segs[q * kSegRow + size_t(nseg)] = make_int2(0, pre);
+    }
     dfree(p->sub_start);
     dfree(p->items);
     dfree(p->iitems);
     dfree(p->hot);
     dfree(p->split_of_tile);
+    dfree(p->item_segs);
     HIP_TRY(upload(&p->sub_start, start), "upload bin offsets");
+    HIP_TRY(upload(&p->item_segs, item_segs), "upload gridding segment tables");
     HIP_TRY(upload(&p->split_of_tile, split_of_tile), "upload split-tile index");
     HIP_TRY(upload(&p->items, items), "upload gridding work items");
     HIP_TRY(upload(&p->hot, hot), "upload split tiles");
@@ -650,6 +676,7 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.grid_elems = p->grid_elems;
     a.partials = p->partials;
     a.n_slots = p->n_slots;
+    a.item_segs = p->item_segs;
     a.mfma = p->grid_mfma;
     a.rec_stride = p->rec_stride;
     HIP_TRY(timed(p, kGrid, s, [&] { return launch_grid(a, s); }), "gridding");

@@ -938,46 +938,18 @@ __device__ __forceinline__ void group_sync(int gsize) {
     }
 }
 
-// The sorted-sample segments that reach tile `tc` (its own bin and the
-// crossing sub-bins of its lower neighbours, in segment_kinds order): bounds
-// loaded one lane per kind, then prefix sums.  Every thread of the workgroup
-// calls it; returns the number of segments.
-template <int DIM>
-__device__ __forceinline__ int grid_item_segments(const GridArgs &a, const int *tc, int *seg_lo, int *seg_hi,
-                                                  int *seg_pre) {
-    // lane q < n_kinds (<= 27) of the first wavefront takes segment kind q; the
-    // offsets of the segments in the item's sample list are a wavefront scan
-    static_assert(kMaxNeighbors <= 64, "one wavefront holds every segment kind");
-    if (threadIdx.x < 64) {
-        const int q = threadIdx.x;
-        int lo = 0, hi = 0;
-        if (q < a.n_kinds) {
-            const int kind = a.kinds[q];
-            int bin = 0;
-#pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) {
-                int b = tc[ax] - ((kind >> ax) & 1);
-                if (b < 0) b += a.nt[ax];
-                bin = bin * a.nt[ax] + b;
-            }
-            const int code = (kind >> 8) & 255;
-            const int base = bin << DIM;
-            lo = a.sub_start[code == 255 ? base : base + code];
-            hi = a.sub_start[code == 255 ? base + (1 << DIM) : base + code + 1];
-        }
-        int incl = hi - lo;  // inclusive prefix of the segment lengths
-#pragma unroll
-        for (int d = 1; d < 32; d <<= 1) {
-            const int t = __shfl_up(incl, d);
-            if (q >= d) incl += t;
-        }
-        if (q < a.n_kinds) {
-            seg_lo[q] = lo;
-            seg_hi[q] = hi;
-            seg_pre[q] = incl - (hi - lo);
-            if (q == a.n_kinds - 1) seg_pre[a.n_kinds] = incl;
-        }
-        if (a.n_kinds == 0 && q == 0) seg_pre[0] = 0;
+// The sorted-sample segments that reach the work item's tile (its own bin and
+// the crossing sub-bins of its lower neighbours, in tile_segments order), from
+// the item's table made when the plan was built: segment starts into seg_lo,
+// their offsets in the item's sample list (and the total) into seg_pre.  Needs
+// nothing from the item record, so both loads are in flight together.  Every
+// thread of the workgroup calls it; returns the number of segments.
+__device__ __forceinline__ int grid_item_segments(const GridArgs &a, int *seg_lo, int *seg_pre) {
+    constexpr int kSegRow = kMaxNeighbors + 1;
+    if (threadIdx.x <= a.n_kinds) {
+        const int2 e = a.item_segs[int64_t(blockIdx.x) * kSegRow + threadIdx.x];
+        seg_lo[threadIdx.x] = e.x;
+        seg_pre[threadIdx.x] = e.y;
     }
     __syncthreads();
     return a.n_kinds;
@@ -1000,10 +972,10 @@ template <int DIM, int LS, int JP>
 __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     extern __shared__ float4 stage_mem[];  // float4: 16-byte aligned rows for the vector reads
     float *stage = reinterpret_cast<float *>(stage_mem);
-    __shared__ int seg_lo[kMaxNeighbors];
-    __shared__ int seg_hi[kMaxNeighbors];
+    __shared__ int seg_lo[kMaxNeighbors + 1];
     __shared__ int seg_pre[kMaxNeighbors + 1];
     const GridItem it = a.items[blockIdx.x];
+    const int nseg = grid_item_segments(a, seg_lo, seg_pre);
     const int g = blockIdx.y;
     const int J = a.geo.J;
     const int L = a.T[DIM - 1];           // cells per tile row
@@ -1032,7 +1004,6 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
             t /= a.nt[ax];
         }
     }
-    const int nseg = grid_item_segments<DIM>(a, tc, seg_lo, seg_hi, seg_pre);
     const int total = seg_pre[nseg];
     const int f0 = it.chunk * a.chunk;
     const int n = min(total, f0 + a.chunk) - f0;
@@ -1223,10 +1194,10 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 template <int DIM, int NJ, int MB>
 __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
     extern __shared__ float mf_lds[];
-    __shared__ int seg_lo[kMaxNeighbors];
-    __shared__ int seg_hi[kMaxNeighbors];
+    __shared__ int seg_lo[kMaxNeighbors + 1];
     __shared__ int seg_pre[kMaxNeighbors + 1];
     const GridItem it = a.items[blockIdx.x];
+    const int nseg = grid_item_segments(a, seg_lo, seg_pre);
     const int g = blockIdx.y;
     const int J = a.geo.J;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
@@ -1243,7 +1214,6 @@ __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
             t /= a.nt[ax];
         }
     }
-    const int nseg = grid_item_segments<DIM>(a, tc, seg_lo, seg_hi, seg_pre);
     const int total = seg_pre[nseg];
     const int f0 = it.chunk * a.chunk;
     const int n = min(total, f0 + a.chunk) - f0;

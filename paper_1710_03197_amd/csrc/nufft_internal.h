@@ -228,6 +228,8 @@ struct GridArgs {
     int64_t grid_elems;
     float2 *partials;     // [grids][n_slots][tile_cells]
     int64_t n_slots;
+    const int2 *item_segs;  // [n_items][kMaxNeighbors + 1]: per segment of the item's tile (first
+                            // sorted sample, offset in the item's list), then (0, total)
     int mfma;             // matrix-core gridding (d >= 2, T_last = 16, 16, 32 or 64 rows)
     int rec_stride;       // its LDS floats per staged sample: 2 + sum of T_a, made odd
 };
