@@ -123,6 +123,7 @@ __device__ __forceinline__ void dft<8>(float2 *v) {
 struct FastDiv {
     unsigned m;
     int d;
+    __device__ __forceinline__ FastDiv() : m(0u), d(1) {}
     __device__ __forceinline__ explicit FastDiv(int D) : m(D > 1 ? 0xFFFFFFFFu / unsigned(D) + 1u : 0u), d(D) {}
     __device__ __forceinline__ FastDiv(unsigned magic, int D) : m(magic), d(D) {}  // magic made on the host
     __device__ __forceinline__ int div(int e) const { return d > 1 ? int(__umulhi(unsigned(e), m)) : e; }
@@ -778,6 +779,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
     int off[SPT];
     bool valid[SPT];
     float2 ph[SPT];
+    int dst[SPT];  // caller's index of the sample (loaded early, used by the final store)
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const int s = threadIdx.x + k * 256;
@@ -786,6 +788,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
         ph[k] = make_float2(1.f, 0.f);
         if (valid[k]) {
             const int64_t i = it.start + s;
+            dst[k] = a.perm[i];
             int o = 0;
 #pragma unroll
             for (int ax = 0; ax < DIM; ++ax) {
@@ -799,25 +802,43 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
             if (a.geo.minmax) ph[k] = mm_phase<DIM>(a.geo, a.om_sorted + i * DIM);
         }
     }
+    // grid index of region element e (tile + halo, wrapped at the grid's edge)
+    FastDiv byE[DIM];
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) byE[ax] = FastDiv(E[ax]);
+    auto grid_index = [&](int e) {
+        int l[DIM];
+#pragma unroll
+        for (int ax = DIM - 1; ax > 0; --ax) {
+            const int q = byE[ax].div(e);
+            l[ax] = byE[ax].rem(e, q);
+            e = q;
+        }
+        l[0] = e;
+        int64_t idx = 0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            int k = base[ax] + l[ax];
+            if (k >= a.geo.K[ax]) k -= a.geo.K[ax];
+            idx = idx * a.geo.K[ax] + k;
+        }
+        return idx;
+    };
     for (int g = 0; g < a.grids; ++g) {
         const float2 *G = a.G + int64_t(g) * a.grid_elems;
         __syncthreads();
-        for (int e = threadIdx.x; e < region; e += 256) {
-            int rem = e;
-            int64_t idx = 0;
-            int l[DIM];
+        // stage the region, eight elements per thread in flight at a time
+        // (indices clamped into the region, so every load is in bounds)
+        constexpr int U = 8;
+        for (int e0 = 0; e0 < region; e0 += U * 256) {
+            float2 v[U];
 #pragma unroll
-            for (int ax = DIM - 1; ax >= 0; --ax) {
-                l[ax] = rem % E[ax];
-                rem /= E[ax];
-            }
+            for (int u = 0; u < U; ++u) v[u] = G[grid_index(min(e0 + u * 256 + int(threadIdx.x), region - 1))];
 #pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) {
-                int k = base[ax] + l[ax];
-                if (k >= a.geo.K[ax]) k -= a.geo.K[ax];
-                idx = idx * a.geo.K[ax] + k;
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * 256 + threadIdx.x;
+                if (e < region) reg[e] = v[u];
             }
-            reg[e] = G[idx];
         }
         __syncthreads();
 #pragma unroll
@@ -852,7 +873,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
                 }
             }
             if (a.geo.minmax) acc = cmul(acc, ph[k]);
-            a.y[int64_t(g) * a.M + a.perm[it.start + threadIdx.x + k * 256]] = acc;
+            a.y[int64_t(g) * a.M + dst[k]] = acc;
         }
     }
 }
