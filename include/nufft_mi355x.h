@@ -107,6 +107,10 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *                 Kaiser-Bessel transform (the same J and beta).  With
  *                 min-max, nufft_grad_points and nufft_density_compensation
  *                 return NUFFT_ERR_UNSUPPORTED.
+ *   interp_merge  most grid tiles along the last axis that one interpolation
+ *                 work item covers when their samples are few (>= 1; the
+ *                 region it stages must fit 64 KiB of LDS, wider runs are
+ *                 cut to what fits); 0: the default (1 for d <= 2, 2 for d = 3)
  * Other values give NUFFT_ERR_INVALID_ARG.
  * Used by the autotuner (paper_1710_03197_amd/autotune.py). */
 typedef struct {
@@ -118,7 +122,8 @@ typedef struct {
     int fuse_reduce;
     int grid_mfma;
     int interpolator;
-    int reserved[2];
+    int interp_merge;
+    int reserved[1];
 } nufft_options_t;
 
 /* nufft_plan with tuning options (opt may be NULL = defaults). */

@@ -125,9 +125,10 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
             if t < best_t:
                 best, best_t = opts, t
     # 2) the gather reading the grid directly instead of staging tiles in LDS,
-    #    and the gridding's samples pre-permuted into sorted order or read
-    #    through the permutation
-    for extra in (dict(interp_direct=1), dict(presort=1), dict(presort=2)):
+    #    the gridding's samples pre-permuted into sorted order or read through
+    #    the permutation, and runs of sparse tiles per gather item
+    for extra in (dict(interp_direct=1), dict(presort=1), dict(presort=2), dict(interp_merge=1),
+                  dict(interp_merge=2), dict(interp_merge=4)):
         opts = dict(best, **extra)
         p = Plan(om, N, K, J, options=opts)
         tried += 1

@@ -120,6 +120,7 @@ struct nufft_plan_s {
     InterpItem *iitems = nullptr;  // nullptr: the gather reads the grid directly
     int64_t n_iitems = 0;
     bool staged_interp = true;
+    int interp_merge = 1;  // tiles along the last axis one gather item may cover
     bool presort = false;      // gridding reads samples permuted into sorted order
     bool fuse_reduce = false;  // first inverse FFT pass sums the partial tiles
     bool grid_mfma = false;    // gridding on the matrix cores
@@ -353,9 +354,33 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
             hot.push_back(HotTile{int(t), slot, nch, 0});
             slots += nch;
         }
-        // gather work items: the tile's own bin in chunks of `ichunk`
-        const int b0 = start[size_t(t) << d], b1 = start[size_t(t + 1) << d];
-        for (int f = b0; f < b1; f += ichunk) iitems.push_back(InterpItem{int(t), f, std::min(ichunk, b1 - f), 0});
+    }
+    // Gather work items: a crowded tile's own bin in chunks of `ichunk`; runs
+    // of sparse tiles along the last axis (their samples are contiguous in the
+    // sorted order) share one item of at most `ichunk` samples and
+    // interp_merge tiles, which stages one region for all of them.
+    {
+        const int nt_last = p->nt[d - 1];
+        int64_t t = 0;
+        while (t < p->nbins) {
+            const int b0 = start[size_t(t) << d], b1 = start[size_t(t + 1) << d];
+            if (b1 - b0 >= ichunk) {
+                for (int f = b0; f < b1; f += ichunk) iitems.push_back(InterpItem{int(t), f, std::min(ichunk, b1 - f), 1});
+                ++t;
+                continue;
+            }
+            if (b1 == b0) {
+                ++t;
+                continue;
+            }
+            int64_t u = t + 1;  // extend the run within the row while it fits
+            while (u < p->nbins && u % nt_last != 0 && u - t < p->interp_merge &&
+                   start[size_t(u + 1) << d] - b0 <= ichunk)
+                ++u;
+            const int e = start[size_t(u) << d];
+            iitems.push_back(InterpItem{int(t), b0, e - b0, int(u - t)});
+            t = u;
+        }
     }
     // Longest items first: workgroups are dealt to the XCDs round-robin in
     // launch order, so the crowded tiles (all at the k-space centre, i.e. at
@@ -635,6 +660,7 @@ int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s)
     a.y = y;
     a.items = p->staged_interp ? p->iitems : nullptr;
     a.n_items = p->n_iitems;
+    a.merge = p->interp_merge;
     for (int ax = 0; ax < p->d; ++ax) {
         a.T[ax] = p->T[ax];
         a.nt[ax] = p->nt[ax];
@@ -1080,6 +1106,7 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     const int need = J - 1;
     p->tile_cells = 1;
     p->nbins = 1;
+    if (opt && opt->interp_merge < 0) return bail(fail(NUFFT_ERR_INVALID_ARG, "interp_merge negative"));
     if (opt && (opt->interpolator < 0 || opt->interpolator > 1))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "interpolator takes 0 (Kaiser-Bessel) or 1 (min-max)"));
     p->minmax = opt && opt->interpolator == 1;
@@ -1152,9 +1179,18 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         p->grid_mfma = mfma_ok && !(opt && opt->grid_mfma == 2);
     }
     {
-        int64_t region = sizeof(float2);
-        for (int a = 0; a < d; ++a) region *= p->T[a] + J - 1;
+        int64_t lead = sizeof(float2);
+        for (int a = 0; a < d - 1; ++a) lead *= p->T[a] + J - 1;
+        const int64_t region = lead * (p->T[d - 1] + J - 1);
         p->staged_interp = region <= kLdsBudget && !(opt && opt->interp_direct);
+        // Runs of sparse tiles per gather item: measured, longer items cost
+        // the latency-bound 2D workload more than the staging they save, the
+        // 3D one gains from pairs.  Cut to what fits the gather's LDS.
+        const int want = (opt && opt->interp_merge > 0) ? opt->interp_merge : (d == 3 ? 2 : 1);
+        p->interp_merge = 1;
+        while (p->interp_merge < std::min(want, p->nt[d - 1]) &&
+               lead * ((p->interp_merge + 1) * p->T[d - 1] + J - 1) <= kInterpLdsBudget)
+            ++p->interp_merge;
     }
     if ((p->nbins << d) >= (int64_t(1) << 30)) return bail(fail(NUFFT_ERR_UNSUPPORTED, "too many bins"));
     p->chunk = d == 3 ? 1024 : 512;

@@ -751,9 +751,10 @@ __device__ __forceinline__ void window_weights(const SampleGeom &geo, const floa
 // spread over the whole chip.
 
 // ------------------------------------------------------------ V (gather)
-// One workgroup per (bin, chunk): the tile and its J-1 halo of the grid are
-// staged in LDS once, then every sample of the chunk (window base inside the
-// tile) reads its J^d taps from LDS.
+// One workgroup per (bin, chunk), or per run of sparse tiles along the last
+// axis: the tiles and their J-1 halo of the grid are staged in LDS once, then
+// every sample of the item (window base inside the tiles) reads its J^d taps
+// from LDS.
 template <int J, int DIM>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
     extern __shared__ float2 reg[];
@@ -771,7 +772,8 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) {
         base[ax] = tc[ax] * a.T[ax];
-        E[ax] = a.T[ax] + J - 1;
+        // a run of it.tiles tiles along the last axis, plus the J - 1 halo
+        E[ax] = (ax == DIM - 1 ? it.tiles : 1) * a.T[ax] + J - 1;
         region *= E[ax];
     }
     constexpr int SPT = kInterpSamplesPerThread;
@@ -1687,7 +1689,7 @@ struct InterpLaunch {
         if (a.items) {
             if (a.n_items == 0) return hipSuccess;
             size_t region = sizeof(float2);
-            for (int ax = 0; ax < DIM; ++ax) region *= size_t(a.T[ax] + J - 1);
+            for (int ax = 0; ax < DIM; ++ax) region *= size_t((ax == DIM - 1 ? a.merge : 1) * a.T[ax] + J - 1);
             hipLaunchKernelGGL((k_interp<J, DIM>), dim3(unsigned(a.n_items)), dim3(256), region, s, a);
         } else {
             const int64_t blocks = (a.M + 255) / 256;

@@ -20,6 +20,7 @@ constexpr int kMaxLinesPerWg = 64;   // lines (contiguous-axis passes) per FFT w
 constexpr int kMaxPolyDeg = 23;
 constexpr int kInterpSamplesPerThread = 2;  // gather work item = 512 samples
 constexpr int kLdsBudget = 64 * 1024;      // bytes of LDS a gather or gridding tile may use
+constexpr int kInterpLdsBudget = 64 * 1024;  // bytes of LDS a gather item covering several tiles may use
 
 // Radix schedule of one FFT axis (Stockham, product of r[] == K).
 // Per pass p (Ns = r[0] ... r[p-1] the length of the sub-transforms done so
@@ -166,10 +167,10 @@ struct SampleGeom {
 // With items, one workgroup per (bin, chunk) stages the tile plus halo in LDS;
 // without (items == nullptr), one thread per sample reads the grid directly.
 struct InterpItem {
-    int bin;
+    int bin;    // first tile
     int start;  // first sorted sample
     int count;  // <= 256 * kInterpSamplesPerThread
-    int pad;
+    int tiles;  // tiles along the last axis the item covers (their samples are contiguous)
 };
 struct InterpArgs {
     SampleGeom geo;
@@ -184,6 +185,7 @@ struct InterpArgs {
     int64_t n_items;
     int T[kMaxDim];
     int nt[kMaxDim];
+    int merge;  // most tiles one item covers (sizes the LDS region)
 };
 hipError_t launch_interp(const InterpArgs &a, hipStream_t s);
 

@@ -68,6 +68,7 @@ class Plan:
         opt.presort = int(self.options.get("presort", 0))
         opt.fuse_reduce = int(self.options.get("fuse_reduce", 0))
         opt.grid_mfma = int(self.options.get("grid_mfma", 0))
+        opt.interp_merge = int(self.options.get("interp_merge", 0))
         interp = self.options.get("interpolator", 0)
         opt.interpolator = {"kb": 0, "kaiser-bessel": 0, "minmax": 1, "min-max": 1}.get(interp, interp) \
             if isinstance(interp, str) else int(interp)

@@ -292,6 +292,9 @@ OPTION_CASES = [
     ((16, 16, 16), dict(tile=(8, 8, 16), grid_mfma=2)),
     ((16, 16, 16), dict(tile=(8, 8, 16), grid_chunk=64, grid_mfma=1, fuse_reduce=2)),
     ((8, 8, 8), dict(tile=(8, 8, 16), grid_mfma=1)),              # last axis one tile
+    ((64, 64), dict(tile=(16, 16), interp_merge=4)),             # gather items over runs of tiles
+    ((16, 16, 16), dict(tile=(8, 8, 8), interp_merge=3)),
+    ((64,), dict(tile=(16,), interp_merge=5)),
 ]
 
 
