@@ -23,6 +23,8 @@
 
 using namespace nufft;
 
+thread_local LaunchEvents *nufft::g_launch_events = nullptr;
+
 namespace {
 
 constexpr uint64_t kMagic = 0x4e55464654333535ull;  // "NUFFT355"
@@ -198,7 +200,8 @@ hipError_t take_event(nufft_plan_s *p, hipEvent_t *ev) {
     return hipEventCreate(ev);
 }
 
-// Launch through `fn`, bracketed by events on `s` when the plan collects timings.
+// Launch through `fn`; when the plan collects timings, its kernel launch
+// stamps a pair of events at the kernel's start and end.
 template <class F>
 hipError_t timed(nufft_plan_s *p, int kernel, hipStream_t s, F fn) {
     if (!p->timing) return fn();
@@ -206,9 +209,16 @@ hipError_t timed(nufft_plan_s *p, int kernel, hipStream_t s, F fn) {
     hipError_t e = take_event(p, &a);
     if (e != hipSuccess) return e;
     if ((e = take_event(p, &b)) != hipSuccess) return e;
-    if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
-    if ((e = fn()) != hipSuccess) return e;
-    if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+    // the stage's kernel launch records a and b at its own start and end
+    LaunchEvents ev{a, b, false};
+    g_launch_events = &ev;
+    e = fn();
+    g_launch_events = nullptr;
+    if (e != hipSuccess || !ev.used) {  // failed, or nothing to launch
+        p->event_pool.push_back(a);
+        p->event_pool.push_back(b);
+        return e;
+    }
     p->timing_recs.push_back({kernel, a, b});
     return hipSuccess;
 }

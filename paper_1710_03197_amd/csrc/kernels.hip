@@ -22,6 +22,7 @@
 //
 // All arithmetic is float32 with float32 accumulation; window positions are
 // float64 (u = omega * K/(2 pi) as one rounded multiply).
+#include <hip/hip_ext.h>
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -30,6 +31,19 @@
 
 namespace nufft {
 namespace {
+
+// Every kernel launch of the library: a launch inside a timed stage carries the
+// stage's start and stop events.
+template <typename K, typename... Args>
+void launch_kernel(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+    LaunchEvents *ev = g_launch_events;
+    if (ev && !ev->used) {
+        ev->used = true;
+        hipExtLaunchKernelGGL(kernel, grid, block, uint32_t(lds), s, ev->start, ev->stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    }
+}
 
 // ------------------------------------------------------------ complex helpers
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -1690,10 +1704,10 @@ struct InterpLaunch {
             if (a.n_items == 0) return hipSuccess;
             size_t region = sizeof(float2);
             for (int ax = 0; ax < DIM; ++ax) region *= size_t((ax == DIM - 1 ? a.merge : 1) * a.T[ax] + J - 1);
-            hipLaunchKernelGGL((k_interp<J, DIM>), dim3(unsigned(a.n_items)), dim3(256), region, s, a);
+            launch_kernel((k_interp<J, DIM>), dim3(unsigned(a.n_items)), dim3(256), region, s, a);
         } else {
             const int64_t blocks = (a.M + 255) / 256;
-            hipLaunchKernelGGL((k_interp_direct<J, DIM>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+            launch_kernel((k_interp_direct<J, DIM>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
         }
         return hipGetLastError();
     }
@@ -1704,7 +1718,7 @@ struct GradLaunch {
     static hipError_t go(const GradArgs &a, hipStream_t s) {
         if (a.M == 0) return hipSuccess;
         const int64_t blocks = (a.M + 255) / 256;
-        hipLaunchKernelGGL((k_grad<J, DIM>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
+        launch_kernel((k_grad<J, DIM>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
         return hipGetLastError();
     }
 };
@@ -1733,7 +1747,7 @@ int threads_for(int elems) {
 template <int T>
 struct FirstGo {
     static hipError_t go(const FirstPassArgs &a, hipStream_t s, int lpw, int64_t, size_t lds, unsigned blocks) {
-        hipLaunchKernelGGL(k_first_pass<T>, dim3(blocks), dim3(T), lds, s, a, lpw);
+        launch_kernel(k_first_pass<T>, dim3(blocks), dim3(T), lds, s, a, lpw);
         return hipGetLastError();
     }
 };
@@ -1741,7 +1755,7 @@ struct FirstGo {
 template <int T>
 struct StridedGoF {
     static hipError_t go(const StridedPassArgs &a, hipStream_t s, int W, int64_t ntc, size_t lds, unsigned blocks) {
-        hipLaunchKernelGGL((k_strided_pass<T, false, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+        launch_kernel((k_strided_pass<T, false, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
         return hipGetLastError();
     }
 };
@@ -1750,9 +1764,9 @@ template <int T>
 struct StridedGoI {
     static hipError_t go(const StridedPassArgs &a, hipStream_t s, int W, int64_t ntc, size_t lds, unsigned blocks) {
         if (a.split_of_tile)
-            hipLaunchKernelGGL((k_strided_pass<T, true, true>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+            launch_kernel((k_strided_pass<T, true, true>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
         else
-            hipLaunchKernelGGL((k_strided_pass<T, true, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
+            launch_kernel((k_strided_pass<T, true, false>), dim3(blocks), dim3(T), lds, s, a, W, ntc);
         return hipGetLastError();
     }
 };
@@ -1793,7 +1807,7 @@ namespace {
 template <int T>
 struct LastGo {
     static hipError_t go(const LastPassArgs &a, hipStream_t s, int rpw, int64_t cpr, size_t lds, unsigned blocks) {
-        hipLaunchKernelGGL(k_last_pass<T>, dim3(blocks), dim3(T), lds, s, a, rpw, int(cpr));
+        launch_kernel(k_last_pass<T>, dim3(blocks), dim3(T), lds, s, a, rpw, int(cpr));
         return hipGetLastError();
     }
 };
@@ -1831,9 +1845,9 @@ hipError_t launch_grid_t(const GridArgs &a, hipStream_t s) {
     const size_t lds = size_t(kGridThreads / a.group_lanes) * a.stage_floats * sizeof(float);
     const dim3 grid(unsigned(a.n_items), unsigned(a.grids));
     if (a.geo.jp == 8)
-        hipLaunchKernelGGL((k_grid<DIM, LS, 8>), grid, dim3(kGridThreads), lds, s, a);
+        launch_kernel((k_grid<DIM, LS, 8>), grid, dim3(kGridThreads), lds, s, a);
     else if (a.geo.jp == 16)
-        hipLaunchKernelGGL((k_grid<DIM, LS, 16>), grid, dim3(kGridThreads), lds, s, a);
+        launch_kernel((k_grid<DIM, LS, 16>), grid, dim3(kGridThreads), lds, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1855,9 +1869,9 @@ hipError_t launch_grid_mfma_j(const GridArgs &a, hipStream_t s) {
     const size_t lds = std::max(size_t(4) * 64 * a.rec_stride, size_t(4) * 2 * cells) * sizeof(float);
     const dim3 grid(unsigned(a.n_items), unsigned(a.grids));
     switch (cells) {
-        case 256: hipLaunchKernelGGL((k_grid_mfma<DIM, NJ, 1>), grid, dim3(256), lds, s, a); break;
-        case 512: hipLaunchKernelGGL((k_grid_mfma<DIM, NJ, 2>), grid, dim3(256), lds, s, a); break;
-        case 1024: hipLaunchKernelGGL((k_grid_mfma<DIM, NJ, 4>), grid, dim3(256), lds, s, a); break;
+        case 256: launch_kernel((k_grid_mfma<DIM, NJ, 1>), grid, dim3(256), lds, s, a); break;
+        case 512: launch_kernel((k_grid_mfma<DIM, NJ, 2>), grid, dim3(256), lds, s, a); break;
+        case 1024: launch_kernel((k_grid_mfma<DIM, NJ, 4>), grid, dim3(256), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1891,7 +1905,7 @@ hipError_t launch_grid(const GridArgs &a, hipStream_t s) {
 
 hipError_t launch_reduce_partials(const ReduceArgs &a, hipStream_t s) {
     if (a.n_hot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(unsigned(a.n_hot), unsigned((a.tile_cells + 255) / 256), unsigned(a.grids)),
+    launch_kernel(k_reduce_partials, dim3(unsigned(a.n_hot), unsigned((a.tile_cells + 255) / 256), unsigned(a.grids)),
                        dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -1903,19 +1917,19 @@ hipError_t launch_grad(const GradArgs &a, hipStream_t s) {
 hipError_t launch_bin_keys(const BinArgs &a, hipStream_t s) {
     if (a.M == 0) return hipSuccess;
     const int64_t blocks = (a.M + 255) / 256;
-    hipLaunchKernelGGL(k_bin_keys, dim3(unsigned(blocks)), dim3(256), 0, s, a);
+    launch_kernel(k_bin_keys, dim3(unsigned(blocks)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, float inv_c, hipStream_t s) {
     if (M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dc_update, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, u, wc, M, inv_c);
+    launch_kernel(k_dc_update, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, u, wc, M, inv_c);
     return hipGetLastError();
 }
 
 hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s) {
     if (M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_real_to_complex, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, wc, M, scale);
+    launch_kernel(k_real_to_complex, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, wc, M, scale);
     return hipGetLastError();
 }
 
@@ -1935,7 +1949,7 @@ static TvGeom tv_geom(int d, const int64_t *N) {
 hipError_t launch_tv_shrink(int d, const int64_t *N, const float2 *x, float2 *dd, float2 *bb, float t, hipStream_t s) {
     const TvGeom g = tv_geom(d, N);
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tv_shrink, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, x, dd, bb, t);
+    launch_kernel(k_tv_shrink, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, x, dd, bb, t);
     return hipGetLastError();
 }
 
@@ -1943,7 +1957,7 @@ hipError_t launch_tv_rhs(int d, const int64_t *N, float mu, const float2 *ahy, c
                          float lam, const float2 *dd, const float2 *bb, float2 *rhs, hipStream_t s) {
     const TvGeom g = tv_geom(d, N);
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tv_rhs, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, mu, ahy, df, bf, lam, dd, bb,
+    launch_kernel(k_tv_rhs, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, mu, ahy, df, bf, lam, dd, bb,
                        rhs);
     return hipGetLastError();
 }
@@ -1952,33 +1966,33 @@ hipError_t launch_tv_normal(int d, const int64_t *N, float mu, const float2 *aha
                             float2 *out, hipStream_t s) {
     const TvGeom g = tv_geom(d, N);
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tv_normal, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, mu, ahax, lam, x, out);
+    launch_kernel(k_tv_normal, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, mu, ahax, lam, x, out);
     return hipGetLastError();
 }
 
 hipError_t launch_bregman_shrink(int64_t n, const float2 *r, float2 *dv, float2 *bv, float t, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bregman_shrink, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, r, dv, bv, t);
+    launch_kernel(k_bregman_shrink, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, r, dv, bv, t);
     return hipGetLastError();
 }
 
 hipError_t launch_iota(int *v, int64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_iota, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, v, n);
+    launch_kernel(k_iota, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, v, n);
     return hipGetLastError();
 }
 
 hipError_t launch_permute_samples(const float2 *y, const int *perm, int64_t M, int grids, float2 *ys,
                                   hipStream_t s) {
     if (M == 0 || grids == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_permute_samples, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, y, perm, M, grids, ys);
+    launch_kernel(k_permute_samples, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, y, perm, M, grids, ys);
     return hipGetLastError();
 }
 
 hipError_t launch_permute_points(const float *om, const int *perm, int64_t M, int d, float *om_sorted,
                                  hipStream_t s) {
     if (M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_permute_points, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, om, perm, M, d,
+    launch_kernel(k_permute_points, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, om, perm, M, d,
                        om_sorted);
     return hipGetLastError();
 }

@@ -235,6 +235,17 @@ struct GridArgs {
     int mfma;             // matrix-core gridding (d >= 2, T_last = 16, 16, 32 or 64 rows)
     int rec_stride;       // its LDS floats per staged sample: 2 + sum of T_a, made odd
 };
+
+// Events a timed stage hands to its kernel launch: the launch has the runtime
+// stamp them at the kernel's own start and end (hipExtLaunchKernel), so the
+// per-kernel timings leave out dispatch and event-record latency.  Set by the
+// plan's timing wrapper around one stage (one kernel), null otherwise; per
+// host thread.
+struct LaunchEvents {
+    hipEvent_t start, stop;
+    bool used;
+};
+extern thread_local LaunchEvents *g_launch_events;
 hipError_t launch_grid(const GridArgs &a, hipStream_t s);
 // ys[g][i] = y[g][perm[i]]: samples into the plan's sorted order.
 hipError_t launch_permute_samples(const float2 *y, const int *perm, int64_t M, int grids, float2 *ys,
