@@ -153,10 +153,16 @@ struct FastDiv {
 // are staged in LDS (tw) once per workgroup.
 constexpr int kEPT = 8;  // complex elements per thread
 
-template <int THREADS, int R, bool INV, bool STRIDED>
-__device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS, int ES, int Ns, int span,
+// KC > 0: the line length KC and sub-transform length NSC of this pass are
+// compile-time constants (the common grid sizes), so its index arithmetic
+// folds; the same operations in the same order as the run-time form.
+template <int THREADS, int R, bool INV, bool STRIDED, int KC = 0, int NSC = 0>
+__device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K_, int LS, int ES, int Ns_, int span_,
                                            unsigned m_ns, unsigned m_nbl, const float2 *tw) {
     constexpr int NB = (kEPT + R - 1) / R;
+    const int K = KC > 0 ? KC : K_;
+    const int Ns = KC > 0 ? NSC : Ns_;
+    const int span = KC > 0 ? KC / ((NSC > 0 ? NSC : 1) * R) : span_;
     const int nbl = K / R;
     const int total = nlines * nbl;
     // (the line count's magic is made per pass: kept across passes it costs
@@ -174,6 +180,9 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
             if (STRIDED) {
                 j = by_line.div(b);
                 line = by_line.rem(b, j);
+            } else if constexpr (KC > 0) {
+                line = b / (KC / R);
+                j = b - line * (KC / R);
             } else {
                 line = by_line.div(b);
                 j = by_line.rem(b, line);
@@ -191,8 +200,14 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
         const int b = threadIdx.x + it * THREADS;
         if (b < total) {
             const int j = jidx[it];
-            const int jq = by_ns.div(j);
-            const int k = by_ns.rem(j, jq);
+            int jq, k;
+            if constexpr (KC > 0) {
+                jq = j / NSC;
+                k = j - jq * NSC;
+            } else {
+                jq = by_ns.div(j);
+                k = by_ns.rem(j, jq);
+            }
             const int step = __umul24(k, span);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -220,6 +235,20 @@ __device__ __forceinline__ void radix_pass(float2 *s, int nlines, int K, int LS,
 
 template <int THREADS, bool INV, bool STRIDED>
 __device__ void lds_fft(float2 *s, int nlines, int K, int LS, int ES, const RadixPlan &rp, const float2 *tw) {
+    // the grid sizes of the common workloads (and their Toeplitz 2N grids)
+    // with their radix plans spelled out at compile time
+    if (K == 512 && rp.n == 3 && rp.r[0] == 8 && rp.r[1] == 8 && rp.r[2] == 8) {
+        radix_pass<THREADS, 8, INV, STRIDED, 512, 1>(s, nlines, K, LS, ES, 1, 0, 0u, 0u, tw);
+        radix_pass<THREADS, 8, INV, STRIDED, 512, 8>(s, nlines, K, LS, ES, 8, 0, 0u, 0u, tw);
+        radix_pass<THREADS, 8, INV, STRIDED, 512, 64>(s, nlines, K, LS, ES, 64, 0, 0u, 0u, tw);
+        return;
+    }
+    if (K == 256 && rp.n == 3 && rp.r[0] == 8 && rp.r[1] == 8 && rp.r[2] == 4) {
+        radix_pass<THREADS, 8, INV, STRIDED, 256, 1>(s, nlines, K, LS, ES, 1, 0, 0u, 0u, tw);
+        radix_pass<THREADS, 8, INV, STRIDED, 256, 8>(s, nlines, K, LS, ES, 8, 0, 0u, 0u, tw);
+        radix_pass<THREADS, 4, INV, STRIDED, 256, 64>(s, nlines, K, LS, ES, 64, 0, 0u, 0u, tw);
+        return;
+    }
     int Ns = 1;
     for (int p = 0; p < rp.n; ++p) {
         const int R = rp.r[p];
