@@ -38,9 +38,15 @@ def _rand_c(shape, seed):
     return (r.standard_normal(shape) + 1j * r.standard_normal(shape)).astype(np.complex64)
 
 
-def _plan(om, N, K, J, dev, coils=None):
+def _plan(om, N, K, J, dev, coils=None, options=None):
     from paper_1710_03197_amd import Plan
-    return Plan(_t(om, dev), N, K, J, coils=None if coils is None else _t(coils, dev))
+    return Plan(_t(om, dev), N, K, J, coils=None if coils is None else _t(coils, dev), options=options)
+
+
+def _bench_options(N, K, J, M):
+    """The plan options bench.py times: the shipped tuning cache's entry."""
+    from paper_1710_03197_amd.autotune import SHIPPED_CACHE, cached_options
+    return cached_options(N, K, J, M, SHIPPED_CACHE)
 
 
 CASES = [
@@ -88,10 +94,13 @@ def test_stagewise_and_pair_parity(orc, dev, name, N, K, J, traj):
     p.close()
 
 
-def test_config2_full_size(orc, dev):
+@pytest.mark.parametrize("tuned", [False, True], ids=["defaults", "bench_options"])
+def test_config2_full_size(orc, dev, tuned):
     c = data.config2()
     N, K, J, om = c["N"], c["K"], c["J"], c["om"]
-    p = _plan(om, N, K, J, dev)
+    opts = _bench_options(N, K, J, om.shape[0]) if tuned else None
+    assert not tuned or opts, "the shipped tuning cache has an entry for this workload"
+    p = _plan(om, N, K, J, dev, options=opts)
     y = _np(p.forward(_t(c["x"], dev)))
     y_o = orc.forward(c["x"], om, N, K, J)
     assert rel_l2(y, y_o) < TOL
@@ -103,10 +112,13 @@ def test_config2_full_size(orc, dev):
     p.close()
 
 
-def test_config3_full_size(orc, dev):
+@pytest.mark.parametrize("tuned", [False, True], ids=["defaults", "bench_options"])
+def test_config3_full_size(orc, dev, tuned):
     c = data.config3()
     N, K, J, om = c["N"], c["K"], c["J"], c["om"]
-    p = _plan(om, N, K, J, dev)
+    opts = _bench_options(N, K, J, om.shape[0]) if tuned else None
+    assert not tuned or opts, "the shipped tuning cache has an entry for this workload"
+    p = _plan(om, N, K, J, dev, options=opts)
     y = _np(p.forward(_t(c["x"], dev)))
     y_o = orc.forward(c["x"], om, N, K, J)
     assert rel_l2(y, y_o) < TOL
@@ -160,6 +172,19 @@ def test_nonfinite_trajectory_rejected(dev):
         p.set_points(_t(om, dev))
     assert np.array_equal(_np(p.forward(x)), y0)  # previous trajectory kept
     p.close()
+
+
+@pytest.mark.parametrize("opts", [dict(interp_merge=-1), dict(fuse_reduce=3), dict(presort=3), dict(grid_chunk=32),
+                                  dict(fft_groups=-1), dict(grid_mfma=3), dict(interpolator=2)],
+                         ids=["interp_merge", "fuse_reduce", "presort", "grid_chunk", "fft_groups", "grid_mfma",
+                              "interpolator"])
+def test_out_of_range_options_rejected(dev, opts):
+    """Every tuning knob outside its documented range is an argument error."""
+    from paper_1710_03197_amd import NufftError, Plan
+    om = np.random.default_rng(3).uniform(-3, 3, (200, 2)).astype(np.float32)
+    with pytest.raises(NufftError) as ei:
+        Plan(_t(om, dev), (16, 16), (32, 32), 6, options=opts)
+    assert ei.value.code == "NUFFT_ERR_INVALID_ARG"
 
 
 def test_batched_equals_looped(dev):
