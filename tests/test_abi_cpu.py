@@ -135,3 +135,20 @@ def test_tv_kernels_reject_null_and_half_lad_arguments():
     assert lib.nufft_bregman_shrink(ctypes.c_int64(-1), dummy, dummy, dummy, f(1.0), None) == -1
     assert lib.nufft_bregman_shrink(ctypes.c_int64(0), None, None, None, f(1.0), None) == 0
     assert lib.nufft_bregman_shrink(ctypes.c_int64(4), dummy, dummy, dummy, f(-2.0), None) == -1
+
+
+def test_options_struct_matches_header():
+    """The Python binding's nufft_options_t has the header's fields, in order,
+    with the same element counts (all int), and the same size."""
+    import re
+    text = open(_lib.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\} nufft_options_t;", text).group(1)
+    fields = []
+    for decl in filter(None, (x.strip() for x in body.split(";"))):
+        m = re.fullmatch(r"int\s+(\w+)(?:\[(\d+)\])?", decl)
+        assert m, decl
+        fields.append((m.group(1), int(m.group(2) or 1)))
+    py = [(name, getattr(ct, "_length_", 1)) for name, ct in _lib.PlanOptions._fields_]
+    assert py == fields
+    assert ctypes.sizeof(_lib.PlanOptions) == 4 * sum(n for _, n in fields)
