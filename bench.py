@@ -38,10 +38,10 @@ TOL = 1e-5
 # has the recorded sha256 prefix and the plan uses the recorded options;
 # otherwise traffic is reported as null.
 MEASURED_TRAFFIC: dict = {
-    "k_grid": {"kernels_sha": "c457eb2db421ab40", "workload": "2d_256_golden_radial",
+    "k_grid": {"kernels_sha": "8a781dc32f0aa520", "workload": "2d_256_golden_radial",
                "options": {"fft_groups": 256, "fuse_reduce": 1, "grid_chunk": 512, "presort": 2, "tile": [16, 16]},
                "fetch_kib": 3407.5, "write_kib": 2254.0, "read_scale": 2.0, "write_scale": 1.0,
-               "bytes_per_launch": 9285821},
+               "bytes_per_launch": 9285771},
 }
 
 

@@ -1444,7 +1444,16 @@ __global__ __launch_bounds__(256) void k_reduce_partials(ReduceArgs a) {
     }
     const float2 *p = a.partials + (int64_t(g) * a.n_slots + ht.slot) * a.tile_cells + e;
     float2 acc = make_float2(0.f, 0.f);
-    for (int c = 0; c < ht.nchunks; ++c) acc = cadd(acc, p[int64_t(c) * a.tile_cells]);
+    // eight partial tiles in flight per round trip, added in chunk order
+    for (int c0 = 0; c0 < ht.nchunks; c0 += 8) {
+        float2 t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (c0 + j < ht.nchunks) t[j] = p[int64_t(c0 + j) * a.tile_cells];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (c0 + j < ht.nchunks) acc = cadd(acc, t[j]);
+    }
     int rem = e;
     int l[kMaxDim];
     for (int ax = a.d - 1; ax >= 0; --ax) {
