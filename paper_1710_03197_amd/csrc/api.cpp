@@ -754,6 +754,8 @@ struct GraphCache {
     std::vector<void *> out;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each launch of exec
+    bool launched = false;
 };
 
 struct nufft_multi_s {
@@ -777,7 +779,12 @@ int check_multi(nufft_multi_t m) {
     return NUFFT_OK;
 }
 
+// Destroys the cached graph.  Its last launch may still be running (calls
+// return before the GPU is done): wait for it first, so no launch outlives
+// the executable graph it runs.
 void drop_graph(GraphCache &gc) {
+    if (gc.launched && gc.done) (void)hipEventSynchronize(gc.done);
+    gc.launched = false;
     if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
     if (gc.graph) (void)hipGraphDestroy(gc.graph);
     gc.exec = nullptr;
@@ -800,6 +807,10 @@ void free_multi(nufft_multi_s *m) {
     (void)hipSetDevice(m->device);
     drop_graph(m->fwd);
     drop_graph(m->adj);
+    for (GraphCache *gc : {&m->fwd, &m->adj}) {
+        if (gc->done) (void)hipEventDestroy(gc->done);
+        gc->done = nullptr;
+    }
     for (auto st : m->streams) (void)hipStreamDestroy(st);
     for (auto ev : m->events) (void)hipEventDestroy(ev);
     m->streams.clear();
@@ -860,7 +871,10 @@ int multi_run(nufft_multi_s *m, bool forward, const void *const *in, void *const
         gc.in.assign(in, in + P);
         gc.out.assign(out, out + P);
     }
+    if (!gc.done) HIP_TRY(hipEventCreateWithFlags(&gc.done, hipEventDisableTiming), "create graph event");
     HIP_TRY(hipGraphLaunch(gc.exec, user), "launch the multi-problem graph");
+    HIP_TRY(hipEventRecord(gc.done, user), "record graph completion");
+    gc.launched = true;
     return NUFFT_OK;
 }
 

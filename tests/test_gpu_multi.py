@@ -21,9 +21,6 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-@pytest.mark.skip(reason="crashed once on MI355X (host segmentation fault inside nufft_multi_adjoint, no GPU "
-                         "fault) while this test re-captured the multi-problem graph for new output buffers; "
-                         "the cause is not found yet, so the case stays off the GPU until it is")
 def test_multi_matches_single_plans_and_oracle(orc, dev):
     from paper_1710_03197_amd.plan import MultiPlan, Plan
     probs = data.config4(seed=41, n_problems=5, n_coils=3, sizes=(32, 48, 64), m_range=(2000, 9000))
