@@ -130,8 +130,13 @@ typedef struct {
 int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, const float *om_dev,
                   const nufft_options_t *opt, void *stream, nufft_plan_t *out);
 
-/* Replace the trajectory (same M) and re-bin it; synchronises `stream`.
- * On NONFINITE the plan keeps its previous trajectory. */
+/* Replace the trajectory (same M) and re-bin it; synchronises `stream` (and
+ * the stream of the plan's previous call).  On NONFINITE the plan keeps its
+ * previous trajectory.  The binning scratch is owned by the plan, and the
+ * work-item tables are rewritten in place when the new ones fit, so a re-bin
+ * allocates device memory only when the new trajectory needs larger tables.
+ * The plan's tables change: a hipGraph captured from this plan's transforms
+ * before the call must not be replayed after it (capture again). */
 int nufft_set_points(nufft_plan_t plan, const float *om_dev, void *stream);
 
 /* Coil mode (Section 2.2, multi-coil): with C >= 1 maps c_dev = complex64
@@ -169,6 +174,14 @@ int nufft_adjoint_batched(nufft_plan_t plan, int B, const void *y_dev, void *x_d
  * the forward was applied to.  Uses the plan's workspace for F S (c_i x). */
 int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev,
                       float *gom_dev, void *stream);
+
+/* The trajectory gradient summed over a batch of B images sharing the
+ * trajectory (Section 2.1, batch mode): x_dev complex64 [B][N^d], gy_dev
+ * complex64 [B][M] ([B][C][M] in coil mode), gom_dev float32 [M][d] =
+ * sum_b of the single-image gradient.  The workspace grows to B * C grids on
+ * the first call with a larger batch (see nufft_reserve). */
+int nufft_grad_points_batched(nufft_plan_t plan, int B, const void *x_dev, const void *gy_dev,
+                              float *gom_dev, void *stream);
 
 /* Stage entry points, for stage-wise checks.  The K^d grid is complex64 in C
  * order (no batching, no coils):

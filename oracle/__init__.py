@@ -340,13 +340,44 @@ def toeplitz_normal(x, om, N, K, J, w=None, fft: bool = False) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ density compensation
-def density_compensation(om, N, K, J, iters: int, w0=None) -> np.ndarray:
-    """Sampling-density weights by the stable iterations of the paper's
-    Section 2.2 ("Density compensation and gridding", after Pipe and Menon):
-    w <- w / (V V^H w) elementwise, from w0 (ones by default), V the oracle
-    interpolator and V^H its gridding with the kernel normalised to peak 1
-    (the paper writes A A^H; Pipe and Menon divide by the gridding kernel's
-    convolution at the samples, which V V^H is)."""
+# Paper Section 2.2, "Density compensation and gridding", Eq. pipe_density:
+# w_{i+1} = w_i / (A A^H w_i), after Pipe and Menon.  Two functions:
+#   density_compensation_aah  the equation as printed, with the whole pair A;
+#   density_compensation_vvh  the reading the GPU library builds: A A^H
+#                             replaced by the interpolator product V V^H.
+# Why the reading: on an evenly spaced radial trajectory the printed map
+# does not settle in float64 -- its fixed-point residual |A A^H w - 1| grows
+# over the iterations and the spread of the weights grows by orders of
+# magnitude (tests/test_oracle_density.py measures both) -- while the V V^H
+# iteration approaches its fixed point monotonically.
+def density_compensation_aah(om, N, K, J, iters: int, w0=None, form: str = "modulus") -> np.ndarray:
+    """The printed iteration w <- w / (A A^H w) elementwise, from w0 (ones by
+    default), A the oracle forward and A^H its adjoint.  For real w the
+    product A A^H w is complex (the image index range [-N/2, N/2) is not
+    symmetric about 0), so the quotient has two readings: form="modulus"
+    divides by |A A^H w| and keeps the weights real; form="complex" divides by
+    the complex value (complex weights).  A zero entry leaves w_m unchanged."""
+    if form not in ("modulus", "complex"):
+        raise ValueError("form is 'modulus' or 'complex'")
+    M = np.asarray(om).shape[0]
+    w = np.ones(M) if w0 is None else np.asarray(w0).copy()
+    if form == "complex":
+        w = w.astype(np.complex128)
+    for _ in range(iters):
+        u = forward(adjoint(np.asarray(w, np.complex128), om, N, K, J), om, N, K, J)
+        if form == "modulus":
+            u = np.abs(u)
+        w = np.where(u != 0, w / np.where(u != 0, u, 1.0), w)
+    return w
+
+
+def density_compensation_vvh(om, N, K, J, iters: int, w0=None) -> np.ndarray:
+    """w <- w / (V V^H w) elementwise, from w0 (ones by default), V the oracle
+    interpolator and V^H its gridding with the kernel normalised to peak 1:
+    Pipe and Menon's iteration, which divides by the gridding kernel's
+    convolution at the samples.  For positive w the product is real and
+    positive; the modulus only removes float64 rounding in the imaginary
+    part."""
     M = np.asarray(om).shape[0]
     c2 = 1.0
     for n, k in zip(N, K):

@@ -68,6 +68,7 @@ _SIGS = {
     "nufft_forward_batched": [_vp, ctypes.c_int, _vp, _vp, _vp],
     "nufft_adjoint_batched": [_vp, ctypes.c_int, _vp, _vp, _vp],
     "nufft_grad_points": [_vp, _vp, _vp, _vp, _vp],
+    "nufft_grad_points_batched": [_vp, ctypes.c_int, _vp, _vp, _vp, _vp],
     "nufft_stage_fs": [_vp, _vp, _vp, _vp],
     "nufft_stage_v": [_vp, _vp, _vp, _vp],
     "nufft_stage_vh": [_vp, _vp, _vp, _vp],

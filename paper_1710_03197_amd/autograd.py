@@ -21,7 +21,10 @@ class NufftFunction(torch.autograd.Function):
     """y = A(om) x for one image ([*N]) or a batch ([B, *N]) on `plan`.
 
     `om` must be the trajectory the plan currently holds (NufftOp keeps them in
-    step); it is an input only so autograd can route its gradient."""
+    step); it is an input only so autograd can route its gradient.  The
+    backward runs on the plan's trajectory; if the plan was re-binned
+    (Plan.set_points) between this forward and its backward, the backward
+    raises instead of returning gradients for the wrong trajectory."""
 
     @staticmethod
     def forward(ctx, x: torch.Tensor, om: torch.Tensor, plan: Plan):
@@ -29,6 +32,7 @@ class NufftFunction(torch.autograd.Function):
         batched = x.dim() == len(plan.N) + 1
         y = plan.forward_batched(x) if batched else plan.forward(x)
         ctx.plan = plan
+        ctx.generation = plan.generation
         ctx.batched = batched
         ctx.save_for_backward(x)
         return y
@@ -37,15 +41,16 @@ class NufftFunction(torch.autograd.Function):
     def backward(ctx, gy: torch.Tensor):
         (x,) = ctx.saved_tensors
         plan: Plan = ctx.plan
+        if plan.generation != ctx.generation:
+            raise RuntimeError("the NUFFT plan was re-binned for another trajectory (set_points) between this "
+                               "forward and its backward; run backward before changing the trajectory")
         gy = gy.contiguous()
         gx = gom = None
         if ctx.needs_input_grad[0]:
             gx = plan.adjoint_batched(gy) if ctx.batched else plan.adjoint(gy)
         if ctx.needs_input_grad[1]:
             if ctx.batched:
-                gom = torch.zeros((plan.M, plan.d), dtype=torch.float32, device=gy.device)
-                for b in range(x.shape[0]):
-                    gom += plan.grad_points(x[b], gy[b].contiguous())
+                gom = plan.grad_points_batched(x, gy)
             else:
                 gom = plan.grad_points(x, gy)
         return gx, gom, None

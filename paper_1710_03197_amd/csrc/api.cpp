@@ -76,6 +76,22 @@ hipError_t upload(T **p, const std::vector<T> &v) {
     return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// Copy v into *p, reusing the buffer when it holds v (capacity *cap in
+// elements, grown, never shrunk): re-binning a trajectory of the same size
+// then allocates nothing.
+template <class T>
+hipError_t upload_into(T **p, size_t *cap, const std::vector<T> &v) {
+    if (v.size() > *cap || !*p) {
+        dfree(*p);
+        *cap = 0;
+        hipError_t e = dmalloc(p, std::max<size_t>(v.size(), 1));
+        if (e != hipSuccess) return e;
+        *cap = std::max<size_t>(v.size(), 1);
+    }
+    if (v.empty()) return hipSuccess;
+    return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
 bool smooth235(int64_t k) {
     for (int p : {2, 3, 5})
         while (k % p == 0) k /= p;
@@ -135,6 +151,13 @@ struct nufft_plan_s {
     int2 *item_segs = nullptr;      // [n_items][kMaxNeighbors + 1]: (segment start, offset in the item's list)
     int64_t n_hot = 0;
     int64_t n_slots = 0;
+    // capacities of the binning tables above (elements; grown, never shrunk)
+    size_t cap_sub_start = 0, cap_items = 0, cap_iitems = 0, cap_hot = 0, cap_split = 0, cap_item_segs = 0;
+    // binning scratch, sized at plan creation, so re-binning allocates nothing
+    int *bkeys = nullptr, *bkeys_sorted = nullptr, *biota = nullptr, *bcounts = nullptr, *bflag = nullptr;
+    void *sort_temp = nullptr;
+    size_t sort_temp_bytes = 0;
+    float *om_prev = nullptr;  // the trajectory in force while a new one is binned
     // coils
     float2 *coils = nullptr;
     int C = 1;
@@ -242,6 +265,14 @@ void free_plan(nufft_plan_s *p) {
         dfree(p->dcoef[a]);
         dfree(p->phase[a]);
     }
+    dfree(p->bkeys);
+    dfree(p->bkeys_sorted);
+    dfree(p->biota);
+    dfree(p->bcounts);
+    dfree(p->bflag);
+    if (p->sort_temp) (void)hipFree(p->sort_temp);
+    p->sort_temp = nullptr;
+    dfree(p->om_prev);
     dfree(p->om);
     dfree(p->om_sorted);
     dfree(p->perm);
@@ -287,23 +318,11 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
     const int64_t nkeys = p->nbins << d;
     if (M > 0) HIP_TRY(hipMemcpyAsync(p->om, om_dev, size_t(M) * d * sizeof(float), hipMemcpyDeviceToDevice, s),
                        "copy trajectory");
-    int *keys = nullptr, *keys_sorted = nullptr, *iota = nullptr, *counts = nullptr, *flag = nullptr;
-    auto cleanup = [&]() {
-        dfree(keys);
-        dfree(keys_sorted);
-        dfree(iota);
-        dfree(counts);
-        dfree(flag);
-    };
+    int *keys = p->bkeys, *keys_sorted = p->bkeys_sorted, *iota = p->biota, *counts = p->bcounts, *flag = p->bflag;
     std::vector<int> hcounts(size_t(nkeys), 0);
     int hflag = 0;
     hipError_t e = hipSuccess;
     do {
-        if ((e = dmalloc(&keys, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
-        if ((e = dmalloc(&keys_sorted, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
-        if ((e = dmalloc(&iota, size_t(std::max<int64_t>(M, 1)))) != hipSuccess) break;
-        if ((e = dmalloc(&counts, size_t(nkeys))) != hipSuccess) break;
-        if ((e = dmalloc(&flag, 1)) != hipSuccess) break;
         if ((e = hipMemsetAsync(counts, 0, size_t(nkeys) * sizeof(int), s)) != hipSuccess) break;
         if ((e = hipMemsetAsync(flag, 0, sizeof(int), s)) != hipSuccess) break;
         BinArgs ba{};
@@ -328,11 +347,12 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
         if (hflag) break;
         if ((e = launch_iota(iota, M, s)) != hipSuccess) break;
-        if ((e = sort_pairs(keys, keys_sorted, iota, p->perm, M, bits_for(nkeys), s)) != hipSuccess) break;
+        if ((e = sort_pairs(keys, keys_sorted, iota, p->perm, M, bits_for(nkeys), p->sort_temp, p->sort_temp_bytes,
+                            s)) != hipSuccess)
+            break;
         if ((e = launch_permute_points(p->om, p->perm, M, d, p->om_sorted, s)) != hipSuccess) break;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
     } while (false);
-    cleanup();
     if (e != hipSuccess) return hip_fail(e, "binning the trajectory");
     if (hflag) return fail(NUFFT_ERR_NONFINITE, "trajectory has a NaN, infinite or out-of-range coordinate");
 
@@ -445,23 +465,17 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         }
         item_segs[q * kSegRow + size_t(nseg)] = make_int2(0, pre);
     }
-    dfree(p->sub_start);
-    dfree(p->items);
-    dfree(p->iitems);
-    dfree(p->hot);
-    dfree(p->split_of_tile);
-    dfree(p->item_segs);
-    HIP_TRY(upload(&p->sub_start, start), "upload bin offsets");
-    HIP_TRY(upload(&p->item_segs, item_segs), "upload gridding segment tables");
-    HIP_TRY(upload(&p->split_of_tile, split_of_tile), "upload split-tile index");
-    HIP_TRY(upload(&p->items, items), "upload gridding work items");
-    HIP_TRY(upload(&p->hot, hot), "upload split tiles");
+    HIP_TRY(upload_into(&p->sub_start, &p->cap_sub_start, start), "upload bin offsets");
+    HIP_TRY(upload_into(&p->item_segs, &p->cap_item_segs, item_segs), "upload gridding segment tables");
+    HIP_TRY(upload_into(&p->split_of_tile, &p->cap_split, split_of_tile), "upload split-tile index");
+    HIP_TRY(upload_into(&p->items, &p->cap_items, items), "upload gridding work items");
+    HIP_TRY(upload_into(&p->hot, &p->cap_hot, hot), "upload split tiles");
     p->n_items = int64_t(items.size());
     p->n_hot = int64_t(hot.size());
     p->n_slots = slots;
     p->n_iitems = 0;
     if (p->staged_interp) {
-        HIP_TRY(upload(&p->iitems, iitems), "upload gather work items");
+        HIP_TRY(upload_into(&p->iitems, &p->cap_iitems, iitems), "upload gather work items");
         p->n_iitems = int64_t(iitems.size());
     }
     return NUFFT_OK;
@@ -1256,8 +1270,19 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         hipError_t e;
         if ((e = dmalloc(&p->om, size_t(std::max<int64_t>(M, 1)) * d)) != hipSuccess ||
             (e = dmalloc(&p->om_sorted, size_t(std::max<int64_t>(M, 1)) * d)) != hipSuccess ||
-            (e = dmalloc(&p->perm, size_t(std::max<int64_t>(M, 1)))) != hipSuccess)
+            (e = dmalloc(&p->perm, size_t(std::max<int64_t>(M, 1)))) != hipSuccess ||
+            (e = dmalloc(&p->om_prev, size_t(std::max<int64_t>(M, 1)) * d)) != hipSuccess)
             return bail(hip_fail(e, "allocate trajectory"));
+        // binning scratch: keys, sorted keys, identity, sub-bin counts, flag and
+        // the radix sort's temporary storage, kept for every later re-bin
+        const size_t m1 = size_t(std::max<int64_t>(M, 1));
+        if ((e = dmalloc(&p->bkeys, m1)) != hipSuccess || (e = dmalloc(&p->bkeys_sorted, m1)) != hipSuccess ||
+            (e = dmalloc(&p->biota, m1)) != hipSuccess ||
+            (e = dmalloc(&p->bcounts, size_t(p->nbins << d))) != hipSuccess ||
+            (e = dmalloc(&p->bflag, 1)) != hipSuccess ||
+            (e = sort_pairs_temp_bytes(M, bits_for(p->nbins << d), &p->sort_temp_bytes)) != hipSuccess ||
+            (e = hipMalloc(&p->sort_temp, std::max<size_t>(p->sort_temp_bytes, 1))) != hipSuccess)
+            return bail(hip_fail(e, "allocate binning scratch"));
     }
     int st = bin_points(p, om_dev, s);
     if (st) return bail(st);
@@ -1272,26 +1297,27 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
 }
 
 int nufft_set_points(nufft_plan_t plan, const float *om_dev, void *stream) {
-    int st = begin_call(plan, stream);
+    int st = check_plan(plan);
+    if (st) return st;
+    const hipStream_t prev_stream = plan->last_stream;
+    st = begin_call(plan, stream);
     if (st) return st;
     if (plan->M > 0 && !om_dev) return fail(NUFFT_ERR_INVALID_ARG, "om is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // keep the previous trajectory if the new one is rejected
-    float *old_om = nullptr;
+    // The tables below are rewritten in place: wait for the plan's previous
+    // call (possibly on another stream) first.  Keep the previous trajectory
+    // if the new one is rejected.
+    if (prev_stream && prev_stream != s) HIP_TRY(hipStreamSynchronize(prev_stream), "wait for the previous call");
     const size_t bytes = size_t(plan->M) * plan->d * sizeof(float);
-    if (plan->M > 0) {
-        HIP_TRY(dmalloc(&old_om, size_t(plan->M) * plan->d), "allocate trajectory backup");
-        HIP_TRY(hipMemcpyAsync(old_om, plan->om, bytes, hipMemcpyDeviceToDevice, s), "backup trajectory");
-    }
+    if (plan->M > 0) HIP_TRY(hipMemcpyAsync(plan->om_prev, plan->om, bytes, hipMemcpyDeviceToDevice, s),
+                             "backup trajectory");
     st = bin_points(plan, om_dev, s);
     if (st) {
         std::string msg = g_last_error;
-        if (old_om) (void)bin_points(plan, old_om, s);
-        dfree(old_om);
+        (void)bin_points(plan, plan->om_prev, s);
         g_last_error = msg;
         return st;
     }
-    dfree(old_om);
     return ensure_workspace(plan, std::max(plan->cap_grids, 1));
 }
 
@@ -1357,15 +1383,19 @@ int nufft_adjoint(nufft_plan_t plan, const void *y_dev, void *x_dev, void *strea
     return nufft_adjoint_batched(plan, 1, y_dev, x_dev, stream);
 }
 
-int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev, float *gom_dev, void *stream) {
+int nufft_grad_points_batched(nufft_plan_t plan, int B, const void *x_dev, const void *gy_dev, float *gom_dev,
+                              void *stream) {
     int st = begin_call(plan, stream);
     if (st) return st;
     if (plan->minmax) return fail(NUFFT_ERR_UNSUPPORTED, "trajectory gradients need the Kaiser-Bessel interpolator");
+    if (B < 1) return fail(NUFFT_ERR_INVALID_ARG, "B must be >= 1");
     if (!x_dev || ((!gy_dev || !gom_dev) && plan->M > 0)) return fail(NUFFT_ERR_INVALID_ARG, "NULL data pointer");
     const int C = plan->coil_mode ? plan->C : 1;
-    if ((st = ensure_workspace(plan, C))) return st;
+    if ((st = ensure_workspace(plan, B * C))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = run_fs(plan, plan_fft(plan), static_cast<const float2 *>(x_dev), 1, plan->grid, s))) return st;
+    // F S (c_i x_b) for every image and coil: B * C grids in [b][i] order, the
+    // order of gy's [B][C][M] rows, which the kernel sums over
+    if ((st = run_fs(plan, plan_fft(plan), static_cast<const float2 *>(x_dev), B, plan->grid, s))) return st;
     GradArgs a{};
     a.geo = plan->geom();
     a.om_sorted = plan->om_sorted;
@@ -1373,11 +1403,15 @@ int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev, 
     a.M = plan->M;
     a.G = plan->grid;
     a.grid_elems = plan->grid_elems;
-    a.grids = C;
+    a.grids = B * C;
     a.gy = static_cast<const float2 *>(gy_dev);
     a.gom = gom_dev;
     HIP_TRY(timed(plan, kGrad, s, [&] { return launch_grad(a, s); }), "trajectory gradient");
     return NUFFT_OK;
+}
+
+int nufft_grad_points(nufft_plan_t plan, const void *x_dev, const void *gy_dev, float *gom_dev, void *stream) {
+    return nufft_grad_points_batched(plan, 1, x_dev, gy_dev, gom_dev, stream);
 }
 
 int nufft_stage_fs(nufft_plan_t plan, const void *x_dev, void *G_dev, void *stream) {

@@ -2035,21 +2035,23 @@ hipError_t launch_permute_points(const float *om, const int *perm, int64_t M, in
     return hipGetLastError();
 }
 
-hipError_t sort_pairs(const int *keys_in, int *keys_out, const int *vals_in, int *vals_out, int64_t n,
-                      int key_bits, hipStream_t s) {
+hipError_t sort_pairs_temp_bytes(int64_t n, int key_bits, size_t *bytes) {
+    *bytes = 0;
     if (n == 0) return hipSuccess;
-    size_t temp = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp, keys_in, keys_out, vals_in, vals_out,
-                                                      int(n), 0, key_bits, s);
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, static_cast<const int *>(nullptr),
+                                              static_cast<int *>(nullptr), static_cast<const int *>(nullptr),
+                                              static_cast<int *>(nullptr), int(n), 0, key_bits);
+}
+
+hipError_t sort_pairs(const int *keys_in, int *keys_out, const int *vals_in, int *vals_out, int64_t n,
+                      int key_bits, void *temp, size_t temp_bytes, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t need = 0;
+    hipError_t e = sort_pairs_temp_bytes(n, key_bits, &need);
     if (e != hipSuccess) return e;
-    void *buf = nullptr;
-    e = hipMalloc(&buf, temp > 0 ? temp : 1);
-    if (e != hipSuccess) return e;
-    e = hipcub::DeviceRadixSort::SortPairs(buf, temp, keys_in, keys_out, vals_in, vals_out, int(n), 0,
-                                           key_bits, s);
-    hipError_t e2 = hipStreamSynchronize(s);
-    (void)hipFree(buf);
-    return e != hipSuccess ? e : e2;
+    if (need > temp_bytes || !temp) return hipErrorInvalidValue;
+    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, int(n), 0,
+                                              key_bits, s);
 }
 
 }  // namespace nufft

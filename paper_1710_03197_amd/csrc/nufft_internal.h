@@ -375,9 +375,11 @@ hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, fl
 hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s);
 hipError_t launch_permute_points(const float *om, const int *perm, int64_t M, int d, float *om_sorted,
                                  hipStream_t s);
-// Stable sort of (key, value) pairs with hipCUB; temp storage is allocated
-// and freed inside (plan time only).
+// Stable sort of (key, value) pairs with hipCUB in caller-owned temporary
+// storage of temp_bytes (sort_pairs_temp_bytes gives the size for n pairs of
+// key_bits-bit keys).  Asynchronous on s; allocates nothing.
+hipError_t sort_pairs_temp_bytes(int64_t n, int key_bits, size_t *bytes);
 hipError_t sort_pairs(const int *keys_in, int *keys_out, const int *vals_in, int *vals_out, int64_t n,
-                      int key_bits, hipStream_t s);
+                      int key_bits, void *temp, size_t temp_bytes, hipStream_t s);
 
 }  // namespace nufft

@@ -55,6 +55,7 @@ class Plan:
         self.N, self.K, self.J, self.d = N, K, int(J), d
         self.M = int(om.shape[0])
         self.C = 0
+        self.generation = 0  # trajectories re-binned into this plan (set_points)
         self._handle = ctypes.c_void_p()
         n_arr = (ctypes.c_int64 * d)(*N)
         k_arr = (ctypes.c_int64 * d)(*K)
@@ -105,9 +106,12 @@ class Plan:
 
     # ------------------------------------------------------------ configuration
     def set_points(self, om: torch.Tensor):
+        """Re-bin the plan for a new trajectory (same M).  Graphs captured from
+        this plan before the call must not be replayed after it."""
         _need(om, torch.float32, (self.M, self.d), "om", self.device)
         with torch.cuda.device(self.device):
             _lib.call("nufft_set_points", self.handle, _ptr(om), _stream(self.device))
+        self.generation += 1
 
     def set_coils(self, coils: torch.Tensor | None):
         with torch.cuda.device(self.device):
@@ -211,12 +215,42 @@ class Plan:
             _lib.call("nufft_grad_points", self.handle, _ptr(x), _ptr(gy), _ptr(g), _stream(self.device))
         return g
 
-    def density_compensation(self, iters: int = 10, w0: torch.Tensor | None = None) -> torch.Tensor:
+    def grad_points_batched(self, x: torch.Tensor, gy: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Trajectory gradient summed over a batch: x [B, *N], gy [B, M] ([B, C, M]
+        with coils) -> float32 [M, d]."""
+        B = int(x.shape[0])
+        _need(x, torch.complex64, (B,) + self.N, "x", self.device)
+        _need(gy, torch.complex64, self._yshape(B), "gy", self.device)
+        g = out if out is not None else torch.empty((self.M, self.d), dtype=torch.float32, device=self.device)
+        _need(g, torch.float32, (self.M, self.d), "gom", self.device)
+        with torch.cuda.device(self.device):
+            _lib.call("nufft_grad_points_batched", self.handle, B, _ptr(x), _ptr(gy), _ptr(g), _stream(self.device))
+        return g
+
+    def density_compensation(self, iters: int = 10, w0: torch.Tensor | None = None,
+                             form: str = "vvh") -> torch.Tensor:
         """Sampling-density weights w (float32 [M]) by `iters` Pipe-Menon steps
-        w <- w / (V V^H w) from w0 (all ones by default); coils ignored."""
+        from w0 (all ones by default), paper Section 2.2, Eq. pipe_density.
+        form="vvh": w <- w / (V V^H w) in the library (nufft_density_compensation;
+        coils ignored).  form="aah": the equation as printed, w <- w / |A A^H w|,
+        composed from this plan's forward and adjoint (no coils); it does not
+        settle on evenly spaced radial sampling, which is why "vvh" is the
+        default."""
         w = (torch.ones(self.M, dtype=torch.float32, device=self.device) if w0 is None
              else w0.detach().to(torch.float32).clone())
         _need(w, torch.float32, (self.M,), "w", self.device)
+        if form == "aah":
+            if self.C:
+                raise ValueError("the printed form A A^H runs on a plan without coils")
+            if iters < 0:
+                raise ValueError("iters must be >= 0")
+            with torch.cuda.device(self.device):
+                for _ in range(int(iters)):
+                    u = self.forward(self.adjoint(w.to(torch.complex64))).abs()
+                    w = torch.where(u != 0, w / torch.where(u != 0, u, torch.ones_like(u)), w)
+            return w
+        if form != "vvh":
+            raise ValueError("form is 'vvh' or 'aah'")
         with torch.cuda.device(self.device):
             _lib.call("nufft_density_compensation", self.handle, int(iters), _ptr(w), _stream(self.device))
         return w

@@ -111,6 +111,45 @@ def test_nufftop_follows_a_new_trajectory(orc, dev):
     assert rel_l2(y1.cpu().numpy(), orc.forward(x.cpu().numpy(), om1, N, K, J)) < 1e-5
 
 
+def test_backward_after_a_rebin_raises(dev):
+    """A backward that would run on a trajectory re-binned after its forward
+    raises instead of returning gradients for the wrong trajectory."""
+    from paper_1710_03197_amd.autograd import NufftOp
+    N, K, J = (16, 16), (32, 32), 6
+    om1 = data.golden_radial_2d(8, 32)
+    om2 = data.perturb(om1, K, np.random.default_rng(5))
+    x = _t((np.random.default_rng(6).standard_normal(N) + 0j).astype(np.complex64), dev).requires_grad_(True)
+    om_a = _t(om1, dev).requires_grad_(True)
+    om_b = _t(om2, dev).requires_grad_(True)
+    op = NufftOp(om_a.detach(), N, K, J)
+    ya = op(x, om_a)
+    yb = op(x, om_b)  # re-bins the plan for om_b
+    yb.abs().sum().backward()  # fine: the plan holds om_b
+    assert om_b.grad is not None
+    with pytest.raises(RuntimeError, match="re-binned"):
+        ya.abs().sum().backward()
+
+
+def test_batched_trajectory_gradient_is_the_sum_of_single_ones(dev):
+    """nufft_grad_points_batched over B images (coil mode) equals the sum of
+    B single-image calls (to float32 rounding)."""
+    from paper_1710_03197_amd import Plan
+    N, K, J, B, C = (24, 24), (48, 48), 6, 3, 2
+    rng = np.random.default_rng(7)
+    om = data.golden_radial_2d(12, 48)
+    M = om.shape[0]
+    coils = data.coil_maps(N, C, rng).astype(np.complex64)
+    xb = (rng.standard_normal((B,) + N) + 1j * rng.standard_normal((B,) + N)).astype(np.complex64)
+    gy = (rng.standard_normal((B, C, M)) + 1j * rng.standard_normal((B, C, M))).astype(np.complex64)
+    with Plan(_t(om, dev), N, K, J, coils=_t(coils, dev)) as p:
+        g = p.grad_points_batched(_t(xb, dev), _t(gy, dev)).cpu().numpy().astype(np.float64)
+        ref = sum(p.grad_points(_t(xb[b], dev), _t(gy[b], dev)).cpu().numpy().astype(np.float64)
+                  for b in range(B))
+    e = rel_l2(g, ref)
+    print(f"batched vs summed single trajectory gradients: rel L2 {e:.2e}", flush=True)
+    assert e < 1e-6
+
+
 def test_config2_cg_matches_oracle(orc, dev):
     """30 CG iterations on config 2.  The iterate of a 30-step Krylov method is
     sensitive to rounding in the operator: the float64 oracle CG moves by
