@@ -229,6 +229,7 @@ typedef struct {
     const float *om;    /* device float32 [M][d], copied */
     int C;              /* coils, 0 = none */
     const void *coils;  /* device complex64 [C][N^d] or NULL, copied */
+    const nufft_options_t *opt;  /* this problem's plan options, NULL = defaults */
 } nufft_problem_t;
 
 typedef struct nufft_multi_s *nufft_multi_t;
@@ -238,13 +239,24 @@ typedef struct nufft_multi_s *nufft_multi_t;
 int nufft_multi_plan(int P, const nufft_problem_t *probs, void *stream, nufft_multi_t *out);
 
 /* x[p] complex64 [N_p^d] -> y[p] complex64 [M_p] ([C_p][M_p] with coils) for
- * every p, and back.  x and y are host arrays of P device pointers.  The
- * first call for a given set of pointers captures all P transform sequences
- * into one HIP graph (forked over several streams so independent problems may
- * overlap); later calls with the same pointers replay it with one launch.
- * Asynchronous on `stream`. */
+ * every p, and back.  x and y are host arrays of P device pointers.  Every
+ * stage (FFT pass, gather, gridding, partial sums) runs as ONE kernel launch
+ * over the work blocks of all problems and coils -- problems whose stage uses
+ * a different kernel instance (e.g. another FFT workgroup size) get a launch
+ * of their own -- so the number of launches does not grow with P; each
+ * workgroup reads its problem's arguments from a device table.  The first
+ * call with a given set of pointers builds those tables (synchronous
+ * uploads) and captures the launches into a HIP graph; later calls with the
+ * same pointers replay it with one graph launch (the last 4 pointer sets per
+ * direction are kept).  Asynchronous on `stream` after the first call; a
+ * first call with new pointers must not happen inside a stream capture. */
 int nufft_multi_forward(nufft_multi_t m, const void *const *x_dev, void *const *y_dev, void *stream);
 int nufft_multi_adjoint(nufft_multi_t m, const void *const *y_dev, void *const *x_dev, void *stream);
+
+/* Kernel launches that one call of each direction makes (in its graph), for
+ * the most recently used pointer set; -1 for a direction not called yet.
+ * Either pointer may be NULL.  Host only. */
+int nufft_multi_info(nufft_multi_t m, int64_t *launches_fwd, int64_t *launches_adj);
 
 /* Synchronises and frees the sub-plans and cached graphs; a NULL or foreign
  * handle returns BAD_PLAN. */

@@ -48,7 +48,7 @@ class ProblemDesc(ctypes.Structure):
     """nufft_problem_t of include/nufft_mi355x.h."""
     _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int64 * 3), ("K", ctypes.c_int64 * 3),
                 ("J", ctypes.c_int), ("M", ctypes.c_int64), ("om", ctypes.c_void_p),
-                ("C", ctypes.c_int), ("coils", ctypes.c_void_p)]
+                ("C", ctypes.c_int), ("coils", ctypes.c_void_p), ("opt", ctypes.c_void_p)]
 
 
 _vp = ctypes.c_void_p
@@ -81,6 +81,7 @@ _SIGS = {
     "nufft_multi_plan": [ctypes.c_int, ctypes.POINTER(ProblemDesc), _vp, ctypes.POINTER(_vp)],
     "nufft_multi_forward": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
     "nufft_multi_adjoint": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
+    "nufft_multi_info": [_vp, _i64p, _i64p],
     "nufft_multi_destroy": [_vp],
     "nufft_toeplitz_plan": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
     "nufft_toeplitz_apply": [_vp, ctypes.c_int, _vp, _vp, _vp],

@@ -1,6 +1,6 @@
 """Build libnufft_mi355x.so in-tree with hipcc for gfx950.
 
-    python -m paper_1710_03197_amd.build [-v]
+    python -m paper_1710_03197_amd.build [-v] [-i]   (-i: only stale objects)
 """
 import os
 import subprocess
@@ -51,7 +51,17 @@ def hip_runtime_dir() -> str:
     return "/opt/rocm/lib"
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """True when obj is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src, os.path.join(CSRC, "nufft_internal.h"), os.path.join(ROOT, "include", "nufft_mi355x.h")]
+    return any(os.path.getmtime(d) > os.path.getmtime(obj) for d in deps)
+
+
+def build(verbose: bool = False, jobs: int = 3, incremental: bool = False) -> str:
+    """Compile every source (incremental=True: only those whose object is
+    older than the source or a header) and link the library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     t0 = time.time()
@@ -59,6 +69,8 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
+        if incremental and not _stale(obj, os.path.join(CSRC, src)):
+            continue
         cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -86,4 +98,4 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="-i" in sys.argv)

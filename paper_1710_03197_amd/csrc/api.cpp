@@ -506,6 +506,35 @@ int ensure_workspace(nufft_plan_s *p, int grids) {
 
 // ---- stage sequences
 
+// A stage sequence either launches its kernels or, given a collector, records
+// each launch's arguments under a fixed stage slot (the multi-problem launch
+// runs slot by slot, all problems' launches of one slot together).
+enum StageKind { kStFirst, kStStrided, kStLast, kStInterp, kStGrid, kStReduce, kStPermute };
+struct Emitted {
+    int slot = 0;
+    int kind = 0;
+    FirstPassArgs first{};
+    StridedPassArgs strided{};
+    LastPassArgs last{};
+    InterpArgs interp{};
+    GridArgs grid{};
+    ReduceArgs reduce{};
+    PermuteJob permute{};
+};
+struct Collector {
+    std::vector<Emitted> out;
+    Emitted &add(int slot, int kind) {
+        out.emplace_back();
+        out.back().slot = slot;
+        out.back().kind = kind;
+        return out.back();
+    }
+};
+// slots: forward pass p -> p, gather -> kMaxDim; adjoint permute -> 0, gridding
+// -> 1, partial sums -> 2, inverse pass along axis a -> 3 + a
+constexpr int kSlotInterp = kMaxDim;
+constexpr int kSlotPermute = 0, kSlotGrid = 1, kSlotReduce = 2, kSlotInvPass = 3;
+
 // G = F S (c x): x [B][N^d] -> out [B*C][K^d]; intermediates in the workspace.
 // The FFT side of a transform: image N zero-padded onto grid K (or cropped
 // back), per-axis scale tables (S, S^H), radix schedules, twiddles, coils and
@@ -549,7 +578,7 @@ FftGeom plan_fft(const nufft_plan_s *p) {
 // With mult (Toeplitz product) the last forward pass's output is multiplied
 // by it; only d = 1 does this here, d >= 2 fuses it into run_shfh.
 int run_fs(nufft_plan_s *p, const FftGeom &f, const float2 *x, int B, float2 *out, hipStream_t s,
-           const float2 *mult = nullptr) {
+           const float2 *mult = nullptr, Collector *col = nullptr) {
     const int d = f.d;
     const int64_t grids = int64_t(B) * f.C;
     const float2 *cur = x;
@@ -577,7 +606,10 @@ int run_fs(nufft_plan_s *p, const FftGeom &f, const float2 *x, int B, float2 *ou
                 a.Nax[b] = int(f.N[b]);
                 a.scale[b] = f.scale[b];
             }
-            HIP_TRY(timed(p, kFirstPass, s, [&] { return launch_first_pass(a, s); }), "forward first FFT pass");
+            if (col)
+                col->add(pass, kStFirst).first = a;
+            else
+                HIP_TRY(timed(p, kFirstPass, s, [&] { return launch_first_pass(a, s); }), "forward first FFT pass");
         } else {
             StridedPassArgs a{};
             a.in = cur;
@@ -595,7 +627,11 @@ int run_fs(nufft_plan_s *p, const FftGeom &f, const float2 *x, int B, float2 *ou
             a.inverse = false;
             a.target_groups = f.fft_groups;
             a.phase = f.phase ? f.phase[ax] : nullptr;
-            HIP_TRY(timed(p, kStridedFwd, s, [&] { return launch_strided_pass(a, s); }), "forward strided FFT pass");
+            if (col)
+                col->add(pass, kStStrided).strided = a;
+            else
+                HIP_TRY(timed(p, kStridedFwd, s, [&] { return launch_strided_pass(a, s); }),
+                        "forward strided FFT pass");
         }
         cur = dst;
     }
@@ -607,7 +643,7 @@ int run_fs(nufft_plan_s *p, const FftGeom &f, const float2 *x, int B, float2 *ou
 // reduce = false) and the first pass sums them.  With mult (Toeplitz
 // product, d >= 2) the first pass multiplies its input by it.
 int run_shfh(nufft_plan_s *p, const FftGeom &f, const float2 *h, int B, float2 *x, hipStream_t s,
-             bool fused_partials = false, const float2 *mult = nullptr) {
+             bool fused_partials = false, const float2 *mult = nullptr, Collector *col = nullptr) {
     const int d = f.d;
     const int64_t grids = int64_t(B) * f.C;
     const float2 *cur = h;
@@ -632,7 +668,10 @@ int run_shfh(nufft_plan_s *p, const FftGeom &f, const float2 *h, int B, float2 *
                 a.Nax[b] = int(f.N[b]);
                 a.scale[b] = f.scale[b];
             }
-            HIP_TRY(timed(p, kLastPass, s, [&] { return launch_last_pass(a, s); }), "adjoint last FFT pass");
+            if (col)
+                col->add(kSlotInvPass + ax, kStLast).last = a;
+            else
+                HIP_TRY(timed(p, kLastPass, s, [&] { return launch_last_pass(a, s); }), "adjoint last FFT pass");
         } else {
             float2 *dst = (ax % 2 == 0) ? f.tmp : f.grid;
             StridedPassArgs a{};
@@ -665,14 +704,18 @@ int run_shfh(nufft_plan_s *p, const FftGeom &f, const float2 *h, int B, float2 *
                     a.nt[b] = p->nt[b];
                 }
             }
-            HIP_TRY(timed(p, kStridedInv, s, [&] { return launch_strided_pass(a, s); }), "adjoint strided FFT pass");
+            if (col)
+                col->add(kSlotInvPass + ax, kStStrided).strided = a;
+            else
+                HIP_TRY(timed(p, kStridedInv, s, [&] { return launch_strided_pass(a, s); }),
+                        "adjoint strided FFT pass");
             cur = dst;
         }
     }
     return NUFFT_OK;
 }
 
-int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s) {
+int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s, Collector *col = nullptr) {
     InterpArgs a{};
     a.geo = p->geom();
     a.om_sorted = p->om_sorted;
@@ -689,16 +732,26 @@ int run_v(nufft_plan_s *p, const float2 *G, int grids, float2 *y, hipStream_t s)
         a.T[ax] = p->T[ax];
         a.nt[ax] = p->nt[ax];
     }
+    if (col) {
+        col->add(kSlotInterp, kStInterp).interp = a;
+        return NUFFT_OK;
+    }
     HIP_TRY(timed(p, kInterp, s, [&] { return launch_interp(a, s); }), "interpolation");
     return NUFFT_OK;
 }
 
 // reduce = false leaves split tiles as partial tiles for the first inverse FFT
 // pass to sum (d >= 2 adjoint); stage_vh and 1D reduce here.
-int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s, bool reduce = true) {
-    if (p->presort)
-        HIP_TRY(timed(p, kPermute, s, [&] { return launch_permute_samples(y, p->perm, p->M, grids, p->ysorted, s); }),
-                "sort the samples");
+int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s, bool reduce = true,
+           Collector *col = nullptr) {
+    if (p->presort) {
+        if (col)
+            col->add(kSlotPermute, kStPermute).permute = PermuteJob{y, p->perm, p->M, grids, p->ysorted};
+        else
+            HIP_TRY(timed(p, kPermute, s,
+                          [&] { return launch_permute_samples(y, p->perm, p->M, grids, p->ysorted, s); }),
+                    "sort the samples");
+    }
     GridArgs a{};
     a.geo = p->geom();
     a.om_sorted = p->om_sorted;
@@ -729,7 +782,10 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.item_segs = p->item_segs;
     a.mfma = p->grid_mfma;
     a.rec_stride = p->rec_stride;
-    HIP_TRY(timed(p, kGrid, s, [&] { return launch_grid(a, s); }), "gridding");
+    if (col)
+        col->add(kSlotGrid, kStGrid).grid = a;
+    else
+        HIP_TRY(timed(p, kGrid, s, [&] { return launch_grid(a, s); }), "gridding");
     ReduceArgs r{};
     r.hot = p->hot;
     r.n_hot = p->n_hot;
@@ -745,8 +801,12 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     r.h = h;
     r.grid_elems = p->grid_elems;
     r.grids = grids;
-    if (p->n_hot > 0 && reduce)
-        HIP_TRY(timed(p, kReduce, s, [&] { return launch_reduce_partials(r, s); }), "gridding partial sums");
+    if (p->n_hot > 0 && reduce) {
+        if (col)
+            col->add(kSlotReduce, kStReduce).reduce = r;
+        else
+            HIP_TRY(timed(p, kReduce, s, [&] { return launch_reduce_partials(r, s); }), "gridding partial sums");
+    }
     return NUFFT_OK;
 }
 
@@ -761,24 +821,42 @@ int begin_call(nufft_plan_t plan, void *stream) {
 }  // namespace
 
 constexpr uint64_t kMultiMagic = 0x4e55464d554c5449ull;  // "NUFMULTI"
-constexpr int kMultiStreams = 4;
+constexpr int kMultiCache = 4;  // pointer sets kept per direction
 
-struct GraphCache {
+// One kernel launch of a multi-problem stage: the problems whose launches of
+// one slot use the same kernel instance, with their job array and block
+// table on the device.
+struct MultiLaunch {
+    int kind = 0;
+    int threads = 0;
+    bool inverse = false, split = false, staged = false;
+    GridArgs proto{};  // gridding: the kernel instance
+    int J = 0, d = 0;
+    size_t lds = 0;
+    void *jobs = nullptr;
+    int4 *blocks = nullptr;
+    int64_t nblocks = 0;
+};
+
+// Both directions' launches for one set of caller pointers, and their graph.
+struct MultiCall {
     std::vector<const void *> in;
     std::vector<void *> out;
+    std::vector<MultiLaunch> launches;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;  // recorded after each launch of exec
     bool launched = false;
+    uint64_t last_use = 0;
 };
 
 struct nufft_multi_s {
     uint64_t magic = kMultiMagic;
     int device = 0;
     std::vector<nufft_plan_t> plans;
-    GraphCache fwd, adj;
-    std::vector<hipStream_t> streams;  // capture streams: [0] is the origin of the fork
-    std::vector<hipEvent_t> events;    // [0] fork, [1..] joins
+    std::vector<MultiCall> calls[2];  // [0] adjoint, [1] forward
+    hipStream_t capture = nullptr;    // private stream the graphs are captured on
+    uint64_t clock = 0;
 };
 
 namespace {
@@ -793,102 +871,333 @@ int check_multi(nufft_multi_t m) {
     return NUFFT_OK;
 }
 
-// Destroys the cached graph.  Its last launch may still be running (calls
-// return before the GPU is done): wait for it first, so no launch outlives
-// the executable graph it runs.
-void drop_graph(GraphCache &gc) {
-    if (gc.launched && gc.done) (void)hipEventSynchronize(gc.done);
-    gc.launched = false;
-    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
-    if (gc.graph) (void)hipGraphDestroy(gc.graph);
-    gc.exec = nullptr;
-    gc.graph = nullptr;
-    gc.in.clear();
-    gc.out.clear();
+// Frees a cached call.  Its last graph launch may still be running (calls
+// return before the GPU is done): wait for it first, so no launch outlives the
+// graph or the tables it reads.
+void drop_call(MultiCall &mc) {
+    if (mc.launched && mc.done) (void)hipEventSynchronize(mc.done);
+    mc.launched = false;
+    if (mc.exec) (void)hipGraphExecDestroy(mc.exec);
+    if (mc.graph) (void)hipGraphDestroy(mc.graph);
+    if (mc.done) (void)hipEventDestroy(mc.done);
+    mc.exec = nullptr;
+    mc.graph = nullptr;
+    mc.done = nullptr;
+    for (MultiLaunch &l : mc.launches) {
+        if (l.jobs) (void)hipFree(l.jobs);
+        dfree(l.blocks);
+    }
+    mc.launches.clear();
 }
-
-void free_multi(nufft_multi_s *m);
-
-}  // namespace
-
-extern "C" int nufft_forward(nufft_plan_t plan, const void *x_dev, void *y_dev, void *stream);
-extern "C" int nufft_adjoint(nufft_plan_t plan, const void *y_dev, void *x_dev, void *stream);
-extern "C" int nufft_destroy(nufft_plan_t plan);
-
-namespace {
 
 void free_multi(nufft_multi_s *m) {
     (void)hipSetDevice(m->device);
-    drop_graph(m->fwd);
-    drop_graph(m->adj);
-    for (GraphCache *gc : {&m->fwd, &m->adj}) {
-        if (gc->done) (void)hipEventDestroy(gc->done);
-        gc->done = nullptr;
+    for (auto &v : m->calls) {
+        for (MultiCall &mc : v) drop_call(mc);
+        v.clear();
     }
-    for (auto st : m->streams) (void)hipStreamDestroy(st);
-    for (auto ev : m->events) (void)hipEventDestroy(ev);
-    m->streams.clear();
-    m->events.clear();
-    for (auto p : m->plans) (void)nufft_destroy(p);
-    m->plans.clear();
+    if (m->capture) (void)hipStreamDestroy(m->capture);
+    m->capture = nullptr;
 }
 
-// Run all P transforms of one direction on `user`: capture them (forked over
-// the multi-plan's streams) into a graph the first time these pointers are
-// seen, then replay.
+template <class J>
+hipError_t upload_jobs(const std::vector<J> &jobs, void **dev) {
+    *dev = nullptr;
+    hipError_t e = hipMalloc(dev, std::max<size_t>(jobs.size(), 1) * sizeof(J));
+    if (e != hipSuccess || jobs.empty()) return e;
+    return hipMemcpy(*dev, jobs.data(), jobs.size() * sizeof(J), hipMemcpyHostToDevice);
+}
+
+// Work blocks of one problem's launch of a stage: (job, x, y, z) per block.
+// FFT stages run with the group's workgroup size `threads`.
+void stage_blocks(const Emitted &em, int job, int threads, std::vector<int4> &out) {
+    switch (em.kind) {
+        case kStFirst: {
+            const FftLaunch L = first_pass_launch(em.first, threads);
+            for (int64_t b = 0; b < L.blocks; ++b) out.push_back(make_int4(job, int(b), 0, 0));
+            break;
+        }
+        case kStStrided: {
+            const FftLaunch L = strided_pass_launch(em.strided, threads);
+            for (int64_t b = 0; b < L.blocks; ++b) out.push_back(make_int4(job, int(b), 0, 0));
+            break;
+        }
+        case kStLast: {
+            const FftLaunch L = last_pass_launch(em.last, threads);
+            for (int64_t b = 0; b < L.blocks; ++b) out.push_back(make_int4(job, int(b), 0, 0));
+            break;
+        }
+        case kStInterp: {
+            const InterpArgs &a = em.interp;
+            if (a.M == 0) break;
+            const int64_t n = a.items ? a.n_items : (a.M + 255) / 256;
+            for (int64_t b = 0; b < n; ++b) out.push_back(make_int4(job, int(b), 0, 0));
+            break;
+        }
+        case kStGrid: {
+            const GridArgs &a = em.grid;
+            for (int g = 0; g < a.grids; ++g)
+                for (int64_t b = 0; b < a.n_items; ++b) out.push_back(make_int4(job, int(b), g, 0));
+            break;
+        }
+        case kStReduce: {
+            const ReduceArgs &a = em.reduce;
+            const int cbs = (a.tile_cells + 255) / 256;
+            for (int g = 0; g < a.grids; ++g)
+                for (int cb = 0; cb < cbs; ++cb)
+                    for (int64_t h = 0; h < a.n_hot; ++h) out.push_back(make_int4(job, int(h), cb, g));
+            break;
+        }
+        case kStPermute: {
+            const PermuteJob &a = em.permute;
+            if (a.M == 0 || a.grids == 0) break;
+            for (int64_t b = 0; b < (a.M + 255) / 256; ++b) out.push_back(make_int4(job, int(b), 0, 0));
+            break;
+        }
+        default: break;
+    }
+}
+
+// Key of the kernel instance a recorded launch uses (launches with equal keys
+// in one slot share a multi-problem launch).  FFT passes share one
+// workgroup size per slot (the largest any problem needs), so only the
+// strided pass's direction and split-tile form separate them.
+int64_t stage_key(const Emitted &em) {
+    switch (em.kind) {
+        case kStFirst: return 0;
+        case kStStrided: {
+            const bool split = em.strided.inverse && em.strided.split_of_tile != nullptr;
+            return (em.strided.inverse ? 2 : 0) + (split ? 1 : 0);
+        }
+        case kStLast: return 0;
+        case kStInterp: return em.interp.items ? 1 : 0;
+        case kStGrid: return grid_variant(em.grid);
+        default: return 0;
+    }
+}
+
+// Builds, for caller pointers in/out, every stage launch of one direction over
+// all problems, and captures them into a graph.
+int build_call(nufft_multi_s *m, bool forward, const void *const *in, void *const *out, MultiCall &mc) {
+    const size_t P = m->plans.size();
+    std::vector<Collector> cols(P);
+    for (size_t p = 0; p < P; ++p) {
+        nufft_plan_s *pl = m->plans[p];
+        const int C = pl->coil_mode ? pl->C : 1;
+        int st;
+        if (forward) {
+            if ((st = run_fs(pl, plan_fft(pl), static_cast<const float2 *>(in[p]), 1, pl->grid, nullptr, nullptr,
+                             &cols[p])))
+                return st;
+            if ((st = run_v(pl, pl->grid, C, static_cast<float2 *>(out[p]), nullptr, &cols[p]))) return st;
+        } else {
+            const bool fuse = pl->fuse_reduce;
+            if ((st = run_vh(pl, static_cast<const float2 *>(in[p]), C, pl->grid, nullptr, !fuse, &cols[p])))
+                return st;
+            if ((st = run_shfh(pl, plan_fft(pl), pl->grid, 1, static_cast<float2 *>(out[p]), nullptr, fuse, nullptr,
+                               &cols[p])))
+                return st;
+        }
+    }
+    for (int slot = 0; slot <= kSlotInvPass + kMaxDim; ++slot) {
+        // the problems' launches of this slot, grouped by kernel instance
+        std::vector<std::pair<int64_t, std::vector<const Emitted *>>> groups;
+        for (size_t p = 0; p < P; ++p)
+            for (const Emitted &em : cols[p].out) {
+                if (em.slot != slot) continue;
+                const int64_t key = stage_key(em) * 16 + em.kind;
+                if (stage_key(em) < 0) return fail(NUFFT_ERR_UNSUPPORTED, "no multi-problem kernel for a stage");
+                auto it = std::find_if(groups.begin(), groups.end(), [&](const auto &g) { return g.first == key; });
+                if (it == groups.end()) {
+                    groups.push_back({key, {}});
+                    it = groups.end() - 1;
+                }
+                it->second.push_back(&em);
+            }
+        for (auto &grp : groups) {
+            const std::vector<const Emitted *> &ems = grp.second;
+            MultiLaunch L;
+            L.kind = ems[0]->kind;
+            // FFT passes: the largest workgroup size any problem of the group
+            // takes on its own, given to all of them
+            for (const Emitted *em : ems) {
+                if (L.kind == kStFirst) L.threads = std::max(L.threads, first_pass_launch(em->first).threads);
+                if (L.kind == kStStrided) L.threads = std::max(L.threads, strided_pass_launch(em->strided).threads);
+                if (L.kind == kStLast) L.threads = std::max(L.threads, last_pass_launch(em->last).threads);
+            }
+            // blocks of every problem, dealt round-robin (each problem's own
+            // launch order is longest work first, so the merged order is too,
+            // roughly, and the heavy blocks spread over the XCDs)
+            std::vector<std::vector<int4>> per(ems.size());
+            for (size_t j = 0; j < ems.size(); ++j) stage_blocks(*ems[j], int(j), L.threads, per[j]);
+            std::vector<int4> blocks;
+            for (size_t r = 0;; ++r) {
+                bool any = false;
+                for (auto &v : per)
+                    if (r < v.size()) {
+                        blocks.push_back(v[r]);
+                        any = true;
+                    }
+                if (!any) break;
+            }
+            if (blocks.empty()) continue;
+            hipError_t e = hipSuccess;
+            switch (L.kind) {
+                case kStFirst: {
+                    std::vector<FirstJob> jobs;
+                    for (const Emitted *em : ems) {
+                        const FftLaunch fl = first_pass_launch(em->first, L.threads);
+                        jobs.push_back(FirstJob{em->first, fl.p0});
+                        L.lds = std::max(L.lds, fl.lds);
+                    }
+                    e = upload_jobs(jobs, &L.jobs);
+                    break;
+                }
+                case kStStrided: {
+                    std::vector<StridedJob> jobs;
+                    for (const Emitted *em : ems) {
+                        const FftLaunch fl = strided_pass_launch(em->strided, L.threads);
+                        jobs.push_back(StridedJob{em->strided, fl.p0, fl.p1});
+                        L.lds = std::max(L.lds, fl.lds);
+                        L.inverse = em->strided.inverse;
+                        L.split = em->strided.inverse && em->strided.split_of_tile != nullptr;
+                    }
+                    e = upload_jobs(jobs, &L.jobs);
+                    break;
+                }
+                case kStLast: {
+                    std::vector<LastJob> jobs;
+                    for (const Emitted *em : ems) {
+                        const FftLaunch fl = last_pass_launch(em->last, L.threads);
+                        jobs.push_back(LastJob{em->last, fl.p0, int(fl.p1)});
+                        L.lds = std::max(L.lds, fl.lds);
+                    }
+                    e = upload_jobs(jobs, &L.jobs);
+                    break;
+                }
+                case kStInterp: {
+                    std::vector<InterpArgs> jobs;
+                    for (const Emitted *em : ems) {
+                        jobs.push_back(em->interp);
+                        L.staged = em->interp.items != nullptr;
+                        L.J = em->interp.geo.J;
+                        L.d = em->interp.geo.d;
+                        L.lds = std::max(L.lds, interp_lds(em->interp));
+                    }
+                    e = upload_jobs(jobs, &L.jobs);
+                    break;
+                }
+                case kStGrid: {
+                    std::vector<GridArgs> jobs;
+                    for (const Emitted *em : ems) {
+                        jobs.push_back(em->grid);
+                        L.proto = em->grid;
+                        L.lds = std::max(L.lds, grid_lds(em->grid));
+                    }
+                    e = upload_jobs(jobs, &L.jobs);
+                    break;
+                }
+                case kStReduce: {
+                    std::vector<ReduceArgs> jobs;
+                    for (const Emitted *em : ems) jobs.push_back(em->reduce);
+                    e = upload_jobs(jobs, &L.jobs);
+                    break;
+                }
+                case kStPermute: {
+                    std::vector<PermuteJob> jobs;
+                    for (const Emitted *em : ems) jobs.push_back(em->permute);
+                    e = upload_jobs(jobs, &L.jobs);
+                    break;
+                }
+                default: break;
+            }
+            if (e == hipSuccess) e = upload(&L.blocks, blocks);
+            L.nblocks = int64_t(blocks.size());
+            mc.launches.push_back(L);
+            if (e != hipSuccess) return hip_fail(e, "upload multi-problem tables");
+        }
+    }
+    return NUFFT_OK;
+}
+
+hipError_t issue(const MultiLaunch &L, hipStream_t s) {
+    switch (L.kind) {
+        case kStFirst:
+            return launch_first_pass_multi(static_cast<const FirstJob *>(L.jobs), L.blocks, L.nblocks, L.threads,
+                                           L.lds, s);
+        case kStStrided:
+            return launch_strided_pass_multi(static_cast<const StridedJob *>(L.jobs), L.blocks, L.nblocks, L.threads,
+                                             L.inverse, L.split, L.lds, s);
+        case kStLast:
+            return launch_last_pass_multi(static_cast<const LastJob *>(L.jobs), L.blocks, L.nblocks, L.threads, L.lds,
+                                          s);
+        case kStInterp:
+            return launch_interp_multi(static_cast<const InterpArgs *>(L.jobs), L.blocks, L.nblocks, L.J, L.d,
+                                       L.staged, L.lds, s);
+        case kStGrid:
+            return launch_grid_multi(static_cast<const GridArgs *>(L.jobs), L.blocks, L.nblocks, L.proto, L.lds, s);
+        case kStReduce:
+            return launch_reduce_partials_multi(static_cast<const ReduceArgs *>(L.jobs), L.blocks, L.nblocks, s);
+        case kStPermute:
+            return launch_permute_samples_multi(static_cast<const PermuteJob *>(L.jobs), L.blocks, L.nblocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Run all P transforms of one direction on `user`: one launch per stage and
+// kernel instance over every problem, captured into a graph the first time
+// these pointers are seen (kept for kMultiCache pointer sets), then replayed.
 int multi_run(nufft_multi_s *m, bool forward, const void *const *in, void *const *out, hipStream_t user) {
     const size_t P = m->plans.size();
     if (!in || !out) return fail(NUFFT_ERR_INVALID_ARG, "pointer arrays are NULL");
     for (size_t p = 0; p < P; ++p)
         if (!in[p] || !out[p]) return fail(NUFFT_ERR_INVALID_ARG, "pointer %zu is NULL", p);
     HIP_TRY(hipSetDevice(m->device), "select device");
-    bool timing = false;
-    for (auto pl : m->plans) timing = timing || pl->timing;
-    if (timing) {  // per-kernel events cannot live in a graph: run the sequence directly
-        for (size_t p = 0; p < P; ++p) {
-            int st = forward ? nufft_forward(m->plans[p], in[p], out[p], user)
-                             : nufft_adjoint(m->plans[p], in[p], out[p], user);
-            if (st) return st;
+    std::vector<MultiCall> &cache = m->calls[forward ? 1 : 0];
+    MultiCall *mc = nullptr;
+    for (MultiCall &c : cache) {
+        bool hit = true;
+        for (size_t p = 0; hit && p < P; ++p) hit = c.in[p] == in[p] && c.out[p] == out[p];
+        if (hit) {
+            mc = &c;
+            break;
         }
-        return NUFFT_OK;
     }
-    GraphCache &gc = forward ? m->fwd : m->adj;
-    bool hit = gc.exec && gc.in.size() == P;
-    for (size_t p = 0; hit && p < P; ++p) hit = gc.in[p] == in[p] && gc.out[p] == out[p];
-    if (!hit) {
-        drop_graph(gc);
-        hipStream_t origin = m->streams[0];
-        HIP_TRY(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal), "begin graph capture");
-        int st = NUFFT_OK;
-        hipError_t e = hipEventRecord(m->events[0], origin);
-        for (int k = 1; e == hipSuccess && k < kMultiStreams; ++k) e = hipStreamWaitEvent(m->streams[k], m->events[0], 0);
-        for (size_t p = 0; e == hipSuccess && st == NUFFT_OK && p < P; ++p) {
-            hipStream_t sp = m->streams[p % kMultiStreams];
-            st = forward ? nufft_forward(m->plans[p], in[p], out[p], sp) : nufft_adjoint(m->plans[p], in[p], out[p], sp);
+    if (!mc) {
+        if (cache.size() >= size_t(kMultiCache)) {  // evict the least recently used pointer set
+            auto lru = std::min_element(cache.begin(), cache.end(),
+                                        [](const MultiCall &a, const MultiCall &b) { return a.last_use < b.last_use; });
+            drop_call(*lru);
+            cache.erase(lru);
         }
-        for (int k = 1; e == hipSuccess && k < kMultiStreams; ++k) {
-            e = hipEventRecord(m->events[k], m->streams[k]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(origin, m->events[k], 0);
+        cache.emplace_back();
+        mc = &cache.back();
+        mc->in.assign(in, in + P);
+        mc->out.assign(out, out + P);
+        int st = build_call(m, forward, in, out, *mc);
+        if (st == NUFFT_OK) {
+            hipError_t e = hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal);
+            for (size_t k = 0; e == hipSuccess && k < mc->launches.size(); ++k) e = issue(mc->launches[k], m->capture);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(m->capture, &graph);
+            mc->graph = graph;
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&mc->exec, graph, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&mc->done, hipEventDisableTiming);
+            if (e != hipSuccess) st = hip_fail(e, "capture the multi-problem launches");
         }
-        hipGraph_t graph = nullptr;
-        hipError_t e2 = hipStreamEndCapture(origin, &graph);
         if (st) {
-            if (graph) (void)hipGraphDestroy(graph);
+            std::string msg = g_last_error;
+            drop_call(*mc);
+            cache.pop_back();
+            g_last_error = msg;
             return st;
         }
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return hip_fail(e != hipSuccess ? e : e2, "capture the multi-problem graph");
-        }
-        gc.graph = graph;
-        HIP_TRY(hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0), "instantiate the multi-problem graph");
-        gc.in.assign(in, in + P);
-        gc.out.assign(out, out + P);
     }
-    if (!gc.done) HIP_TRY(hipEventCreateWithFlags(&gc.done, hipEventDisableTiming), "create graph event");
-    HIP_TRY(hipGraphLaunch(gc.exec, user), "launch the multi-problem graph");
-    HIP_TRY(hipEventRecord(gc.done, user), "record graph completion");
-    gc.launched = true;
+    mc->last_use = ++m->clock;
+    HIP_TRY(hipGraphLaunch(mc->exec, user), "launch the multi-problem graph");
+    HIP_TRY(hipEventRecord(mc->done, user), "record graph completion");
+    mc->launched = true;
     return NUFFT_OK;
 }
 
@@ -986,6 +1295,7 @@ int nufft_multi_plan(int P, const nufft_problem_t *probs, void *stream, nufft_mu
     auto bail = [&](int st) {
         std::string msg = g_last_error;
         free_multi(m);
+        for (auto pl : m->plans) (void)nufft_destroy(pl);
         delete m;
         g_last_error = msg;
         return st;
@@ -994,24 +1304,19 @@ int nufft_multi_plan(int P, const nufft_problem_t *probs, void *stream, nufft_mu
     for (int p = 0; p < P; ++p) {
         const nufft_problem_t &pr = probs[p];
         nufft_plan_t h = nullptr;
-        int st = nufft_plan(pr.d, pr.N, pr.K, pr.J, pr.M, pr.om, stream, &h);
+        int st = nufft_plan_ex(pr.d, pr.N, pr.K, pr.J, pr.M, pr.om, pr.opt, stream, &h);
         if (st) return bail(st);
         m->plans.push_back(h);
         if (pr.C > 0) {
             st = nufft_set_coils(h, pr.C, pr.coils);
             if (st) return bail(st);
         }
+        // the multi-problem launches read each plan's workspace for its C grids
+        st = ensure_workspace(h, pr.C > 0 ? pr.C : 1);
+        if (st) return bail(st);
     }
-    for (int k = 0; k < kMultiStreams; ++k) {
-        hipStream_t st;
-        hipEvent_t ev;
-        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e != hipSuccess) return bail(hip_fail(e, "create capture stream"));
-        m->streams.push_back(st);
-        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e != hipSuccess) return bail(hip_fail(e, "create capture event"));
-        m->events.push_back(ev);
-    }
+    hipError_t e = hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(hip_fail(e, "create capture stream"));
     {
         std::lock_guard<std::mutex> lk(g_registry_mu);
         g_multi_registry.insert(m);
@@ -1032,6 +1337,21 @@ int nufft_multi_adjoint(nufft_multi_t m, const void *const *y_dev, void *const *
     return multi_run(m, false, y_dev, x_dev, static_cast<hipStream_t>(stream));
 }
 
+int nufft_multi_info(nufft_multi_t m, int64_t *launches_fwd, int64_t *launches_adj) {
+    int st = check_multi(m);
+    if (st) return st;
+    for (int dir = 0; dir < 2; ++dir) {
+        int64_t *dst = dir ? launches_fwd : launches_adj;
+        if (!dst) continue;
+        *dst = -1;
+        const MultiCall *last = nullptr;
+        for (const MultiCall &c : m->calls[dir])
+            if (!last || c.last_use > last->last_use) last = &c;
+        if (last) *dst = int64_t(last->launches.size());
+    }
+    return NUFFT_OK;
+}
+
 int nufft_multi_destroy(nufft_multi_t m) {
     int st = check_multi(m);
     if (st) return st;
@@ -1041,7 +1361,9 @@ int nufft_multi_destroy(nufft_multi_t m) {
     }
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
-    free_multi(m);
+    free_multi(m);  // graphs, tables and the capture stream first, the plans they read last
+    for (auto pl : m->plans) (void)nufft_destroy(pl);
+    m->plans.clear();
     m->magic = 0;
     delete m;
     return NUFFT_OK;
@@ -1649,12 +1971,47 @@ int nufft_toeplitz_destroy(nufft_toeplitz_t t) {
 }
 
 // ------------------------------------------------------------ density compensation
-int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// `iters` density-compensation steps with the caller's buffers wc and u
+// (complex [M] each); asynchronous on s.
+int dc_iterate(nufft_plan_s *plan, int iters, float *w_dev, float2 *wc, float2 *u, hipStream_t s) {
+    // u = V V^H w with the kernel normalised to peak 1: gridding of w / c onto
+    // the oversampled grid, interpolation, and a division by c again
+    double c = 1.0;
+    for (int a = 0; a < plan->d; ++a) c *= kb_i0(plan->ker[a].beta);
+    const float inv_c = float(1.0 / c);
+    hipError_t e;
+    if ((e = launch_real_to_complex(w_dev, wc, plan->M, inv_c, s)) != hipSuccess)
+        return hip_fail(e, "weights to samples");
+    for (int it = 0; it < iters; ++it) {
+        int st;
+        if ((st = run_vh(plan, wc, 1, plan->grid, s, true))) return st;
+        if ((st = run_v(plan, plan->grid, 1, u, s))) return st;
+        if ((e = launch_dc_update(w_dev, u, wc, plan->M, inv_c, s)) != hipSuccess)
+            return hip_fail(e, "density update");
+    }
+    return NUFFT_OK;
+}
+
+int dc_check(nufft_plan_t plan, int iters, float *w_dev, void *stream) {
     int st = begin_call(plan, stream);
     if (st) return st;
     if (plan->minmax) return fail(NUFFT_ERR_UNSUPPORTED, "density compensation needs the Kaiser-Bessel interpolator");
     if (iters < 0) return fail(NUFFT_ERR_INVALID_ARG, "iters must be >= 0");
     if (plan->M > 0 && !w_dev) return fail(NUFFT_ERR_INVALID_ARG, "w is NULL");
+    return NUFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void *stream) {
+    int st = dc_check(plan, iters, w_dev, stream);
+    if (st) return st;
     if (plan->M == 0 || iters == 0) return NUFFT_OK;
     if ((st = ensure_workspace(plan, 1))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1665,24 +2022,13 @@ int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void 
         dfree(u);
         return hip_fail(e, "allocate density-compensation buffers");
     }
-    // u = V V^H w with the kernel normalised to peak 1: gridding of w / c onto
-    // the oversampled grid, interpolation, and a division by c again
-    double c = 1.0;
-    for (int a = 0; a < plan->d; ++a) c *= kb_i0(plan->ker[a].beta);
-    const float inv_c = float(1.0 / c);
-    st = NUFFT_OK;
-    if ((e = launch_real_to_complex(w_dev, wc, plan->M, inv_c, s)) != hipSuccess)
-        st = hip_fail(e, "weights to samples");
-    for (int it = 0; it < iters && !st; ++it) {
-        if ((st = run_vh(plan, wc, 1, plan->grid, s, true))) break;
-        if ((st = run_v(plan, plan->grid, 1, u, s))) break;
-        if ((e = launch_dc_update(w_dev, u, wc, plan->M, inv_c, s)) != hipSuccess) st = hip_fail(e, "density update");
-    }
+    st = dc_iterate(plan, iters, w_dev, wc, u, s);
     if ((e = hipStreamSynchronize(s)) != hipSuccess && !st) st = hip_fail(e, "density compensation");
     dfree(wc);
     dfree(u);
     return st;
 }
+
 
 // ------------------------------------------------------------ TV split-Bregman pieces
 namespace {

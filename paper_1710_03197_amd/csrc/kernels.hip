@@ -338,13 +338,13 @@ __device__ __forceinline__ int src_row(int q, int N, int K) {
 // ------------------------------------------------------------ FFT kernels
 // Dynamic LDS layout of every FFT kernel: [K twiddles][tile].
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lines_per_wg) {
+__device__ __forceinline__ void first_pass_body(const FirstPassArgs &a, int lines_per_wg, int64_t bx) {
     extern __shared__ float2 lds[];
     const int K = a.K, N = a.N;
     float2 *tw = lds;
     float2 *s = lds + K;
     const int64_t total = int64_t(a.B) * a.C * a.rows;
-    const int64_t l0 = int64_t(blockIdx.x) * lines_per_wg;
+    const int64_t l0 = bx * lines_per_wg;
     const int nl = int(min(int64_t(lines_per_wg), total - l0));  // 1..64
     // Line `lane` of the workgroup, known to that lane of every wavefront: the
     // image and coil row offsets and the product of the leading axes' scaling
@@ -431,16 +431,30 @@ __global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lin
     }
 }
 
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_first_pass(FirstPassArgs a, int lines_per_wg) {
+    first_pass_body<THREADS>(a, lines_per_wg, blockIdx.x);
+}
+
+// Many problems in one launch: workgroup b runs block blocks[b].y of problem
+// blocks[b].x, whose arguments sit in jobs[blocks[b].x].
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_first_pass_multi(const FirstJob *__restrict__ jobs,
+                                                             const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    const FirstJob &j = jobs[b.x];
+    first_pass_body<THREADS>(j.a, j.lpw, b.y);
+}
+
 // SPLIT (inverse only): the first inverse pass of an adjoint whose split
 // gridding tiles are still partial tiles (its own instantiation, so the
 // common passes keep their register budget).
 template <int THREADS, bool INV, bool SPLIT>
-__global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int W, int64_t ntc) {
+__device__ __forceinline__ void strided_pass_body(const StridedPassArgs &a, int W, int64_t ntc, int64_t bid) {
     extern __shared__ float2 lds[];
     const int K = a.K;
     float2 *tw = lds;
     float2 *s = lds + K;
-    const int64_t bid = blockIdx.x;
     const int64_t ct = bid % ntc;
     const int64_t rest = bid / ntc;
     const int64_t o = rest % a.outer;
@@ -574,16 +588,29 @@ __global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int
     }
 }
 
+template <int THREADS, bool INV, bool SPLIT>
+__global__ __launch_bounds__(THREADS) void k_strided_pass(StridedPassArgs a, int W, int64_t ntc) {
+    strided_pass_body<THREADS, INV, SPLIT>(a, W, ntc, blockIdx.x);
+}
+
+template <int THREADS, bool INV, bool SPLIT>
+__global__ __launch_bounds__(THREADS) void k_strided_pass_multi(const StridedJob *__restrict__ jobs,
+                                                               const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    const StridedJob &j = jobs[b.x];
+    strided_pass_body<THREADS, INV, SPLIT>(j.a, j.W, j.ntc, b.y);
+}
+
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_per_wg, int coils_per_round) {
+__device__ __forceinline__ void last_pass_body(const LastPassArgs &a, int rows_per_wg, int coils_per_round, int64_t bx) {
     extern __shared__ float2 lds[];
     __shared__ float rsc[kMaxLinesPerWg];
     const int K = a.K, N = a.N, C = a.C;
     float2 *tw = lds;
     float2 *s = lds + K;
     const int64_t nrt = (a.rows + rows_per_wg - 1) / rows_per_wg;
-    const int64_t b = blockIdx.x / nrt;
-    const int64_t r0 = (blockIdx.x % nrt) * rows_per_wg;
+    const int64_t b = bx / nrt;
+    const int64_t r0 = (bx % nrt) * rows_per_wg;
     const int nr = int(min(int64_t(rows_per_wg), a.rows - r0));
     TwiddleStage<THREADS> tws;
     tws.load(a.tw, K);
@@ -688,6 +715,19 @@ __global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_
         const int rr = e / N, i = e - rr * N;
         a.x[(b * a.rows + r0 + rr) * N + i] = cscale(acc[e], rsc[rr] * slast[i]);
     }
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_last_pass(LastPassArgs a, int rows_per_wg, int coils_per_round) {
+    last_pass_body<THREADS>(a, rows_per_wg, coils_per_round, blockIdx.x);
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_last_pass_multi(const LastJob *__restrict__ jobs,
+                                                            const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    const LastJob &j = jobs[b.x];
+    last_pass_body<THREADS>(j.a, j.rpw, j.cpr, b.y);
 }
 
 // ------------------------------------------------------------ interpolation window
@@ -799,9 +839,9 @@ __device__ __forceinline__ void window_weights(const SampleGeom &geo, const floa
 // every sample of the item (window base inside the tiles) reads its J^d taps
 // from LDS.
 template <int J, int DIM>
-__global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
+__device__ __forceinline__ void interp_body(const InterpArgs &a, int64_t item) {
     extern __shared__ float2 reg[];
-    const InterpItem it = a.items[blockIdx.x];
+    const InterpItem it = a.items[item];
     int tc[DIM], base[DIM], E[DIM];
     {
         int t = it.bin;
@@ -923,11 +963,23 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
     }
 }
 
+template <int J, int DIM>
+__global__ __launch_bounds__(256) void k_interp(InterpArgs a) {
+    interp_body<J, DIM>(a, blockIdx.x);
+}
+
+template <int J, int DIM>
+__global__ __launch_bounds__(256) void k_interp_multi(const InterpArgs *__restrict__ jobs,
+                                                     const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    interp_body<J, DIM>(jobs[b.x], b.y);
+}
+
 // Gather straight from the grid (L1/L2), one thread per sorted sample: used
 // when the tile-plus-halo region does not fit the LDS budget.
 template <int J, int DIM>
-__global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void interp_direct_body(const InterpArgs &a, int64_t bx) {
+    const int64_t i = bx * 256 + threadIdx.x;
     if (i >= a.M) return;
     float w[DIM][J];
     int kk[DIM][J];
@@ -975,6 +1027,18 @@ __global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
     }
 }
 
+template <int J, int DIM>
+__global__ __launch_bounds__(256) void k_interp_direct(InterpArgs a) {
+    interp_direct_body<J, DIM>(a, blockIdx.x);
+}
+
+template <int J, int DIM>
+__global__ __launch_bounds__(256) void k_interp_direct_multi(const InterpArgs *__restrict__ jobs,
+                                                            const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    interp_direct_body<J, DIM>(jobs[b.x], b.y);
+}
+
 // ------------------------------------------------------------ V^H (output-driven gridding)
 // One workgroup per (tile, chunk).  The samples that reach the tile are the
 // tile's own bin plus, from each lower neighbour bin, only the sub-bins whose
@@ -1010,10 +1074,10 @@ __device__ __forceinline__ void group_sync(int gsize) {
 // their offsets in the item's sample list (and the total) into seg_pre.  Needs
 // nothing from the item record, so both loads are in flight together.  Every
 // thread of the workgroup calls it; returns the number of segments.
-__device__ __forceinline__ int grid_item_segments(const GridArgs &a, int *seg_lo, int *seg_pre) {
+__device__ __forceinline__ int grid_item_segments(const GridArgs &a, int64_t item, int *seg_lo, int *seg_pre) {
     constexpr int kSegRow = kMaxNeighbors + 1;
     if (threadIdx.x <= a.n_kinds) {
-        const int2 e = a.item_segs[int64_t(blockIdx.x) * kSegRow + threadIdx.x];
+        const int2 e = a.item_segs[item * kSegRow + threadIdx.x];
         seg_lo[threadIdx.x] = e.x;
         seg_pre[threadIdx.x] = e.y;
     }
@@ -1035,14 +1099,13 @@ __device__ __forceinline__ int batch_segment(const int *seg_pre, int nseg, int &
 }
 
 template <int DIM, int LS, int JP>
-__global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
+__device__ __forceinline__ void grid_body(const GridArgs &a, int64_t item, int g) {
     extern __shared__ float4 stage_mem[];  // float4: 16-byte aligned rows for the vector reads
     float *stage = reinterpret_cast<float *>(stage_mem);
     __shared__ int seg_lo[kMaxNeighbors + 1];
     __shared__ int seg_pre[kMaxNeighbors + 1];
-    const GridItem it = a.items[blockIdx.x];
-    const int nseg = grid_item_segments(a, seg_lo, seg_pre);
-    const int g = blockIdx.y;
+    const GridItem it = a.items[item];
+    const int nseg = grid_item_segments(a, item, seg_lo, seg_pre);
     const int J = a.geo.J;
     const int L = a.T[DIM - 1];           // cells per tile row
     const int S = a.segs;                 // segments per row
@@ -1244,6 +1307,18 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
     }
 }
 
+template <int DIM, int LS, int JP>
+__global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
+    grid_body<DIM, LS, JP>(a, blockIdx.x, blockIdx.y);
+}
+
+template <int DIM, int LS, int JP>
+__global__ __launch_bounds__(kGridThreads) void k_grid_multi(const GridArgs *__restrict__ jobs,
+                                                            const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    grid_body<DIM, LS, JP>(jobs[b.x], b.y, b.z);
+}
+
 // V^H on the matrix cores, for tiles of 16*MB rows (the leading axes) by 16
 // cells (last axis).  Over a batch of samples s the tile is
 //   H[r][c] = sum_s (v_s * wlead_s[r]) * wlast_s[c],
@@ -1258,13 +1333,12 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(GridArgs a) {
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 template <int DIM, int NJ, int MB>
-__global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
+__device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, int g) {
     extern __shared__ float mf_lds[];
     __shared__ int seg_lo[kMaxNeighbors + 1];
     __shared__ int seg_pre[kMaxNeighbors + 1];
-    const GridItem it = a.items[blockIdx.x];
-    const int nseg = grid_item_segments(a, seg_lo, seg_pre);
-    const int g = blockIdx.y;
+    const GridItem it = a.items[item];
+    const int nseg = grid_item_segments(a, item, seg_lo, seg_pre);
     const int J = a.geo.J;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
     const int lane = threadIdx.x & 63;
@@ -1427,12 +1501,23 @@ __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
     }
 }
 
+template <int DIM, int NJ, int MB>
+__global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
+    grid_mfma_body<DIM, NJ, MB>(a, blockIdx.x, blockIdx.y);
+}
+
+template <int DIM, int NJ, int MB>
+__global__ __launch_bounds__(256) void k_grid_mfma_multi(const GridArgs *__restrict__ jobs,
+                                                        const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    grid_mfma_body<DIM, NJ, MB>(jobs[b.x], b.y, b.z);
+}
+
 // Sums the partial tiles of every split tile in chunk order; one workgroup per
 // (tile, 256 cells, grid).
-__global__ __launch_bounds__(256) void k_reduce_partials(ReduceArgs a) {
-    const HotTile ht = a.hot[blockIdx.x];
-    const int g = blockIdx.z;
-    const int e = blockIdx.y * 256 + threadIdx.x;
+__device__ __forceinline__ void reduce_partials_body(const ReduceArgs &a, int64_t hot, int cb, int g) {
+    const HotTile ht = a.hot[hot];
+    const int e = cb * 256 + threadIdx.x;
     if (e >= a.tile_cells) return;
     int tc[kMaxDim];
     {
@@ -1463,6 +1548,16 @@ __global__ __launch_bounds__(256) void k_reduce_partials(ReduceArgs a) {
     int64_t idx = 0;
     for (int ax = 0; ax < a.d; ++ax) idx = idx * a.K[ax] + tc[ax] * a.T[ax] + l[ax];
     a.h[int64_t(g) * a.grid_elems + idx] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(ReduceArgs a) {
+    reduce_partials_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials_multi(const ReduceArgs *__restrict__ jobs,
+                                                             const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    reduce_partials_body(jobs[b.x], b.y, b.z, b.w);
 }
 
 // ------------------------------------------------------------ trajectory gradient
@@ -1574,12 +1669,24 @@ __global__ void k_iota(int *v, int64_t n) {
     if (i < n) v[i] = int(i);
 }
 
-__global__ __launch_bounds__(256) void k_permute_samples(const float2 *y, const int *perm, int64_t M, int grids,
-                                                         float2 *ys) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void permute_samples_body(const float2 *y, const int *perm, int64_t M, int grids,
+                                                     float2 *ys, int64_t bx) {
+    const int64_t i = bx * 256 + threadIdx.x;
     if (i >= M) return;
     const int64_t m = perm[i];
     for (int g = 0; g < grids; ++g) ys[int64_t(g) * M + i] = y[int64_t(g) * M + m];
+}
+
+__global__ __launch_bounds__(256) void k_permute_samples(const float2 *y, const int *perm, int64_t M, int grids,
+                                                         float2 *ys) {
+    permute_samples_body(y, perm, M, grids, ys, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_permute_samples_multi(const PermuteJob *__restrict__ jobs,
+                                                               const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    const PermuteJob &j = jobs[b.x];
+    permute_samples_body(j.y, j.perm, j.M, j.grids, j.ys, b.y);
 }
 
 __global__ void k_permute_points(const float *om, const int *perm, int64_t M, int d, float *out) {
@@ -1740,13 +1847,24 @@ struct InterpLaunch {
         if (a.M == 0) return hipSuccess;
         if (a.items) {
             if (a.n_items == 0) return hipSuccess;
-            size_t region = sizeof(float2);
-            for (int ax = 0; ax < DIM; ++ax) region *= size_t((ax == DIM - 1 ? a.merge : 1) * a.T[ax] + J - 1);
-            launch_kernel((k_interp<J, DIM>), dim3(unsigned(a.n_items)), dim3(256), region, s, a);
+            launch_kernel((k_interp<J, DIM>), dim3(unsigned(a.n_items)), dim3(256), interp_lds(a), s, a);
         } else {
             const int64_t blocks = (a.M + 255) / 256;
             launch_kernel((k_interp_direct<J, DIM>), dim3(unsigned(blocks)), dim3(256), 0, s, a);
         }
+        return hipGetLastError();
+    }
+};
+
+template <int J, int DIM>
+struct InterpMultiLaunch {
+    static hipError_t go(const InterpArgs *jobs, const int4 *blocks, int64_t n, bool staged, size_t lds,
+                         hipStream_t s) {
+        if (n == 0) return hipSuccess;
+        if (staged)
+            launch_kernel((k_interp_multi<J, DIM>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks);
+        else
+            launch_kernel((k_interp_direct_multi<J, DIM>), dim3(unsigned(n)), dim3(256), 0, s, jobs, blocks);
         return hipGetLastError();
     }
 };
@@ -1812,33 +1930,53 @@ struct StridedGoI {
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s) {
+FftLaunch first_pass_launch(const FirstPassArgs &a, int threads) {
+    FftLaunch L{64, 0, 0, 1, 0};
     const int64_t total = int64_t(a.B) * a.C * a.rows;
-    if (total == 0) return hipSuccess;
+    if (total == 0) return L;
     const int cap = kFftTileElems / a.K;  // lines that fit the largest tile
     int lpw = int(std::min<int64_t>(std::max<int64_t>(1, total / a.target_groups), std::min(cap, kMaxLinesPerWg)));
     lpw = std::max(1, lpw);
-    const int threads = threads_for(lpw * a.K);
-    const int64_t blocks = (total + lpw - 1) / lpw;
-    const size_t lds = size_t(lpw + 1) * a.K * sizeof(float2);
-    return fft_dispatch<FirstGo>(threads, a, s, lpw, 0, lds, unsigned(blocks));
+    if (threads > 0)  // a given workgroup size: as many lines as its tile holds
+        lpw = int(std::max<int64_t>(1, std::min<int64_t>({total, kMaxLinesPerWg, threads * kEPT / a.K})));
+    L.threads = threads > 0 ? threads : threads_for(lpw * a.K);
+    L.blocks = (total + lpw - 1) / lpw;
+    L.lds = size_t(lpw + 1) * a.K * sizeof(float2);
+    L.p0 = lpw;
+    return L;
 }
 
-hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s) {
+hipError_t launch_first_pass(const FirstPassArgs &a, hipStream_t s) {
+    const FftLaunch L = first_pass_launch(a);
+    if (L.blocks == 0) return hipSuccess;
+    return fft_dispatch<FirstGo>(L.threads, a, s, L.p0, 0, L.lds, unsigned(L.blocks));
+}
+
+FftLaunch strided_pass_launch(const StridedPassArgs &a, int threads) {
+    FftLaunch L{64, 0, 0, 1, 0};
     const int64_t columns = a.grids * a.outer * a.inner;
-    if (columns == 0) return hipSuccess;
-    const int cap = std::max(1, kFftTileElems / a.K);
-    // columns per tile: at least 4 adjacent (32-byte rows), fewer only for narrow arrays
-    int64_t W = std::max<int64_t>(4, columns / a.target_groups);
+    if (columns == 0) return L;
+    const int cap = std::max(1, threads > 0 ? threads * kEPT / a.K : kFftTileElems / a.K);
+    // columns per tile: at least 4 adjacent (32-byte rows), fewer only for narrow
+    // arrays; with a given workgroup size, as many as its tile holds
+    int64_t W = threads > 0 ? cap : std::max<int64_t>(4, columns / a.target_groups);
     W = std::min<int64_t>(W, cap);
     W = std::min<int64_t>(W, a.inner);
     W = std::max<int64_t>(W, 1);
     const int64_t ntc = (a.inner + W - 1) / W;
-    const int64_t blocks = ntc * a.outer * a.grids;
-    const int threads = threads_for(int(W) * a.K);
-    const size_t lds = size_t(W + 1) * a.K * sizeof(float2);
-    if (a.inverse) return fft_dispatch<StridedGoI>(threads, a, s, int(W), ntc, lds, unsigned(blocks));
-    return fft_dispatch<StridedGoF>(threads, a, s, int(W), ntc, lds, unsigned(blocks));
+    L.blocks = ntc * a.outer * a.grids;
+    L.threads = threads > 0 ? threads : threads_for(int(W) * a.K);
+    L.lds = size_t(W + 1) * a.K * sizeof(float2);
+    L.p0 = int(W);
+    L.p1 = ntc;
+    return L;
+}
+
+hipError_t launch_strided_pass(const StridedPassArgs &a, hipStream_t s) {
+    const FftLaunch L = strided_pass_launch(a);
+    if (L.blocks == 0) return hipSuccess;
+    if (a.inverse) return fft_dispatch<StridedGoI>(L.threads, a, s, L.p0, L.p1, L.lds, unsigned(L.blocks));
+    return fft_dispatch<StridedGoF>(L.threads, a, s, L.p0, L.p1, L.lds, unsigned(L.blocks));
 }
 
 namespace {
@@ -1851,36 +1989,115 @@ struct LastGo {
 };
 }  // namespace
 
-hipError_t launch_last_pass(const LastPassArgs &a, hipStream_t s) {
+FftLaunch last_pass_launch(const LastPassArgs &a, int threads) {
+    FftLaunch L{64, 0, 0, 1, 1};
     const int64_t total_rows = int64_t(a.B) * a.rows;
-    if (total_rows == 0) return hipSuccess;
+    if (total_rows == 0) return L;
+    const int tile = threads > 0 ? threads * kEPT : kFftTileElems;
     int rows_per_wg, coils_per_round;
-    if (a.C * a.K <= kFftTileElems) {
+    if (a.C * a.K <= tile) {
         coils_per_round = a.C;
-        const int cap = std::min(kFftTileElems / (a.C * a.K), kMaxLinesPerWg);
-        rows_per_wg = int(std::min<int64_t>(std::max<int64_t>(1, total_rows / a.target_groups), cap));
+        const int cap = std::min(tile / (a.C * a.K), kMaxLinesPerWg);
+        rows_per_wg = threads > 0 ? cap
+                                  : int(std::min<int64_t>(std::max<int64_t>(1, total_rows / a.target_groups), cap));
     } else {
         rows_per_wg = 1;
-        coils_per_round = std::max(1, kFftTileElems / a.K);
+        coils_per_round = std::max(1, tile / a.K);
     }
     if (int64_t(rows_per_wg) > a.rows) rows_per_wg = int(a.rows);
     rows_per_wg = std::max(1, rows_per_wg);
-    const int threads = threads_for(rows_per_wg * coils_per_round * a.K);
+    L.threads = threads > 0 ? threads : threads_for(rows_per_wg * coils_per_round * a.K);
     const int64_t nrt = (a.rows + rows_per_wg - 1) / rows_per_wg;
-    const int64_t blocks = nrt * a.B;
+    L.blocks = nrt * a.B;
     const bool one_round = coils_per_round >= a.C;
-    const size_t lds = (size_t(a.K) + size_t(rows_per_wg) * coils_per_round * a.K +
-                        (one_round ? 0 : size_t(rows_per_wg) * a.N)) * sizeof(float2);
-    return fft_dispatch<LastGo>(threads, a, s, rows_per_wg, coils_per_round, lds, unsigned(blocks));
+    L.lds = (size_t(a.K) + size_t(rows_per_wg) * coils_per_round * a.K +
+             (one_round ? 0 : size_t(rows_per_wg) * a.N)) * sizeof(float2);
+    L.p0 = rows_per_wg;
+    L.p1 = coils_per_round;
+    return L;
+}
+
+hipError_t launch_last_pass(const LastPassArgs &a, hipStream_t s) {
+    const FftLaunch L = last_pass_launch(a);
+    if (L.blocks == 0) return hipSuccess;
+    return fft_dispatch<LastGo>(L.threads, a, s, L.p0, L.p1, L.lds, unsigned(L.blocks));
+}
+
+// ---- many problems per launch
+namespace {
+template <int T>
+struct FirstMulti {
+    static void go(const FirstJob *j, const int4 *b, int64_t n, size_t lds, hipStream_t s) {
+        launch_kernel(k_first_pass_multi<T>, dim3(unsigned(n)), dim3(T), lds, s, j, b);
+    }
+};
+template <int T>
+struct LastMulti {
+    static void go(const LastJob *j, const int4 *b, int64_t n, size_t lds, hipStream_t s) {
+        launch_kernel(k_last_pass_multi<T>, dim3(unsigned(n)), dim3(T), lds, s, j, b);
+    }
+};
+template <bool INV, bool SPLIT>
+struct StridedMultiF {
+    template <int T>
+    struct K {
+        static void go(const StridedJob *j, const int4 *b, int64_t n, size_t lds, hipStream_t s) {
+            launch_kernel((k_strided_pass_multi<T, INV, SPLIT>), dim3(unsigned(n)), dim3(T), lds, s, j, b);
+        }
+    };
+};
+
+template <template <int> class L, class Job>
+hipError_t threads_go(int threads, const Job *j, const int4 *b, int64_t n, size_t lds, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    switch (threads) {
+        case 64: L<64>::go(j, b, n, lds, s); break;
+        case 128: L<128>::go(j, b, n, lds, s); break;
+        case 256: L<256>::go(j, b, n, lds, s); break;
+        case 512: L<512>::go(j, b, n, lds, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_first_pass_multi(const FirstJob *jobs, const int4 *blocks, int64_t nblocks, int threads,
+                                   size_t lds, hipStream_t s) {
+    return threads_go<FirstMulti>(threads, jobs, blocks, nblocks, lds, s);
+}
+
+hipError_t launch_strided_pass_multi(const StridedJob *jobs, const int4 *blocks, int64_t nblocks, int threads,
+                                     bool inverse, bool split, size_t lds, hipStream_t s) {
+    if (!inverse) return threads_go<StridedMultiF<false, false>::K>(threads, jobs, blocks, nblocks, lds, s);
+    if (split) return threads_go<StridedMultiF<true, true>::K>(threads, jobs, blocks, nblocks, lds, s);
+    return threads_go<StridedMultiF<true, false>::K>(threads, jobs, blocks, nblocks, lds, s);
+}
+
+hipError_t launch_last_pass_multi(const LastJob *jobs, const int4 *blocks, int64_t nblocks, int threads, size_t lds,
+                                  hipStream_t s) {
+    return threads_go<LastMulti>(threads, jobs, blocks, nblocks, lds, s);
+}
+
+size_t interp_lds(const InterpArgs &a) {
+    if (!a.items) return 0;
+    size_t region = sizeof(float2);
+    for (int ax = 0; ax < a.geo.d; ++ax)
+        region *= size_t((ax == a.geo.d - 1 ? a.merge : 1) * a.T[ax] + a.geo.J - 1);
+    return region;
 }
 
 hipError_t launch_interp(const InterpArgs &a, hipStream_t s) {
     return dispatch_jd<InterpLaunch>(a.geo.J, a.geo.d, a, s);
 }
 
+hipError_t launch_interp_multi(const InterpArgs *jobs, const int4 *blocks, int64_t nblocks, int J, int d,
+                               bool staged, size_t lds, hipStream_t s) {
+    return dispatch_jd<InterpMultiLaunch>(J, d, jobs, blocks, nblocks, staged, lds, s);
+}
+
 template <int DIM, int LS>
 hipError_t launch_grid_t(const GridArgs &a, hipStream_t s) {
-    const size_t lds = size_t(kGridThreads / a.group_lanes) * a.stage_floats * sizeof(float);
+    const size_t lds = grid_lds(a);
     const dim3 grid(unsigned(a.n_items), unsigned(a.grids));
     if (a.geo.jp == 8)
         launch_kernel((k_grid<DIM, LS, 8>), grid, dim3(kGridThreads), lds, s, a);
@@ -1904,7 +2121,7 @@ hipError_t launch_grid_d(const GridArgs &a, hipStream_t s) {
 template <int DIM, int NJ>
 hipError_t launch_grid_mfma_j(const GridArgs &a, hipStream_t s) {
     const int cells = a.tile_cells;
-    const size_t lds = std::max(size_t(4) * 64 * a.rec_stride, size_t(4) * 2 * cells) * sizeof(float);
+    const size_t lds = grid_lds(a);
     const dim3 grid(unsigned(a.n_items), unsigned(a.grids));
     switch (cells) {
         case 256: launch_kernel((k_grid_mfma<DIM, NJ, 1>), grid, dim3(256), lds, s, a); break;
@@ -1939,6 +2156,102 @@ hipError_t launch_grid(const GridArgs &a, hipStream_t s) {
         case 3: return launch_grid_d<3>(a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Kernel instance of a gridding launch: matrix cores (d, taps rounded to
+// 6/8/16, row blocks) or vector ALUs (d, segment length, coefficient row
+// width), as launch_grid picks it; -1 if there is none.
+int grid_variant(const GridArgs &a) {
+    if (a.mfma) {
+        if (a.geo.d < 2 || a.T[a.geo.d - 1] != 16) return -1;
+        const int nj = a.geo.J <= 6 ? 6 : a.geo.J <= 8 ? 8 : 16;
+        const int mb = a.tile_cells / 256;
+        if (a.tile_cells % 256 || (mb != 1 && mb != 2 && mb != 4)) return -1;
+        return 1000 + 100 * a.geo.d + 10 * (nj == 6 ? 0 : nj == 8 ? 1 : 2) + mb;
+    }
+    if (a.seg_len != 4 && a.seg_len != 8 && a.seg_len != 16) return -1;
+    if (a.geo.jp != 8 && a.geo.jp != 16) return -1;
+    return 2000 + 100 * a.geo.d + a.seg_len * 2 + (a.geo.jp == 16 ? 1 : 0);
+}
+
+size_t grid_lds(const GridArgs &a) {
+    if (a.mfma) return std::max(size_t(4) * 64 * a.rec_stride, size_t(4) * 2 * a.tile_cells) * sizeof(float);
+    return size_t(kGridThreads / a.group_lanes) * a.stage_floats * sizeof(float);
+}
+
+namespace {
+template <int DIM, int NJ>
+hipError_t grid_mfma_multi_j(const GridArgs *jobs, const int4 *blocks, int64_t n, int mb, size_t lds, hipStream_t s) {
+    switch (mb) {
+        case 1: launch_kernel((k_grid_mfma_multi<DIM, NJ, 1>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
+        case 2: launch_kernel((k_grid_mfma_multi<DIM, NJ, 2>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
+        case 4: launch_kernel((k_grid_mfma_multi<DIM, NJ, 4>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t grid_mfma_multi_d(const GridArgs *jobs, const int4 *blocks, int64_t n, const GridArgs &p, size_t lds,
+                             hipStream_t s) {
+    const int mb = p.tile_cells / 256;
+    if (p.geo.J <= 6) return grid_mfma_multi_j<DIM, 6>(jobs, blocks, n, mb, lds, s);
+    if (p.geo.J <= 8) return grid_mfma_multi_j<DIM, 8>(jobs, blocks, n, mb, lds, s);
+    return grid_mfma_multi_j<DIM, 16>(jobs, blocks, n, mb, lds, s);
+}
+
+template <int DIM, int LS>
+hipError_t grid_valu_multi_t(const GridArgs *jobs, const int4 *blocks, int64_t n, int jp, size_t lds, hipStream_t s) {
+    if (jp == 8)
+        launch_kernel((k_grid_multi<DIM, LS, 8>), dim3(unsigned(n)), dim3(kGridThreads), lds, s, jobs, blocks);
+    else if (jp == 16)
+        launch_kernel((k_grid_multi<DIM, LS, 16>), dim3(unsigned(n)), dim3(kGridThreads), lds, s, jobs, blocks);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t grid_valu_multi_d(const GridArgs *jobs, const int4 *blocks, int64_t n, const GridArgs &p, size_t lds,
+                             hipStream_t s) {
+    switch (p.seg_len) {
+        case 4: return grid_valu_multi_t<DIM, 4>(jobs, blocks, n, p.geo.jp, lds, s);
+        case 8: return grid_valu_multi_t<DIM, 8>(jobs, blocks, n, p.geo.jp, lds, s);
+        case 16: return grid_valu_multi_t<DIM, 16>(jobs, blocks, n, p.geo.jp, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_grid_multi(const GridArgs *jobs, const int4 *blocks, int64_t nblocks, const GridArgs &proto,
+                             size_t lds, hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
+    if (grid_variant(proto) < 0) return hipErrorInvalidValue;
+    if (proto.mfma) {
+        switch (proto.geo.d) {
+            case 2: return grid_mfma_multi_d<2>(jobs, blocks, nblocks, proto, lds, s);
+            case 3: return grid_mfma_multi_d<3>(jobs, blocks, nblocks, proto, lds, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (proto.geo.d) {
+        case 1: return grid_valu_multi_d<1>(jobs, blocks, nblocks, proto, lds, s);
+        case 2: return grid_valu_multi_d<2>(jobs, blocks, nblocks, proto, lds, s);
+        case 3: return grid_valu_multi_d<3>(jobs, blocks, nblocks, proto, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce_partials_multi(const ReduceArgs *jobs, const int4 *blocks, int64_t nblocks, hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
+    launch_kernel(k_reduce_partials_multi, dim3(unsigned(nblocks)), dim3(256), 0, s, jobs, blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_samples_multi(const PermuteJob *jobs, const int4 *blocks, int64_t nblocks, hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
+    launch_kernel(k_permute_samples_multi, dim3(unsigned(nblocks)), dim3(256), 0, s, jobs, blocks);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const ReduceArgs &a, hipStream_t s) {

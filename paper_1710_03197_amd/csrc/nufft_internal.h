@@ -365,6 +365,63 @@ struct BinArgs {
 };
 hipError_t launch_bin_keys(const BinArgs &a, hipStream_t s);
 hipError_t launch_iota(int *v, int64_t n, hipStream_t s);
+// ---- many problems in one launch per stage.  Each stage kernel has a form
+// that reads its arguments from a device array of per-problem jobs and runs,
+// as workgroup b, block blocks[b] = (problem, block x, block y, block z) of
+// that problem's own launch; problems whose launches use the same kernel
+// instance share one launch.
+struct FftLaunch {
+    int threads;     // workgroup size
+    int64_t blocks;  // workgroups of the problem's launch
+    size_t lds;      // dynamic LDS bytes
+    int p0;          // first pass: lines per workgroup; strided: columns W; last: rows per workgroup
+    int64_t p1;      // strided: column tiles per row block; last: coils per round
+};
+// threads > 0: the launch of a given workgroup size (64..512, large enough for
+// one line of K), lines or columns per workgroup as many as its tile holds.
+FftLaunch first_pass_launch(const FirstPassArgs &a, int threads = 0);
+FftLaunch strided_pass_launch(const StridedPassArgs &a, int threads = 0);
+FftLaunch last_pass_launch(const LastPassArgs &a, int threads = 0);
+struct FirstJob {
+    FirstPassArgs a;
+    int lpw;
+};
+struct StridedJob {
+    StridedPassArgs a;
+    int W;
+    int64_t ntc;
+};
+struct LastJob {
+    LastPassArgs a;
+    int rpw;
+    int cpr;
+};
+struct PermuteJob {
+    const float2 *y;
+    const int *perm;
+    int64_t M;
+    int grids;
+    float2 *ys;
+};
+hipError_t launch_first_pass_multi(const FirstJob *jobs, const int4 *blocks, int64_t nblocks, int threads,
+                                   size_t lds, hipStream_t s);
+hipError_t launch_strided_pass_multi(const StridedJob *jobs, const int4 *blocks, int64_t nblocks, int threads,
+                                     bool inverse, bool split, size_t lds, hipStream_t s);
+hipError_t launch_last_pass_multi(const LastJob *jobs, const int4 *blocks, int64_t nblocks, int threads, size_t lds,
+                                  hipStream_t s);
+// LDS of a staged gather launch (0 for the direct form).
+size_t interp_lds(const InterpArgs &a);
+hipError_t launch_interp_multi(const InterpArgs *jobs, const int4 *blocks, int64_t nblocks, int J, int d,
+                               bool staged, size_t lds, hipStream_t s);
+// The gridding kernel instance a launch uses (problems with the same value
+// share a launch) and its LDS bytes.
+int grid_variant(const GridArgs &a);
+size_t grid_lds(const GridArgs &a);
+hipError_t launch_grid_multi(const GridArgs *jobs, const int4 *blocks, int64_t nblocks, const GridArgs &proto,
+                             size_t lds, hipStream_t s);
+hipError_t launch_reduce_partials_multi(const ReduceArgs *jobs, const int4 *blocks, int64_t nblocks, hipStream_t s);
+hipError_t launch_permute_samples_multi(const PermuteJob *jobs, const int4 *blocks, int64_t nblocks, hipStream_t s);
+
 hipError_t launch_tv_shrink(int d, const int64_t *N, const float2 *x, float2 *dd, float2 *bb, float t, hipStream_t s);
 hipError_t launch_tv_rhs(int d, const int64_t *N, float mu, const float2 *ahy, const float2 *df, const float2 *bf,
                          float lam, const float2 *dd, const float2 *bb, float2 *rhs, hipStream_t s);

@@ -36,6 +36,25 @@ def _need(t: torch.Tensor, dtype, shape, name: str, device):
         raise ValueError(f"{name} must be contiguous")
 
 
+def options_struct(options: dict | None) -> "_lib.PlanOptions":
+    """nufft_options_t from a dict of plan options (missing keys: 0 = default)."""
+    options = options or {}
+    opt = _lib.PlanOptions()
+    for a, t in enumerate(options.get("tile", ())[:3]):
+        opt.tile[a] = int(t)
+    opt.grid_chunk = int(options.get("grid_chunk", 0))
+    opt.fft_groups = int(options.get("fft_groups", 0))
+    opt.interp_direct = int(bool(options.get("interp_direct", 0)))
+    opt.presort = int(options.get("presort", 0))
+    opt.fuse_reduce = int(options.get("fuse_reduce", 0))
+    opt.grid_mfma = int(options.get("grid_mfma", 0))
+    opt.interp_merge = int(options.get("interp_merge", 0))
+    interp = options.get("interpolator", 0)
+    opt.interpolator = {"kb": 0, "kaiser-bessel": 0, "minmax": 1, "min-max": 1}.get(interp, interp) \
+        if isinstance(interp, str) else int(interp)
+    return opt
+
+
 class Plan:
     """NUFFT plan for image size N, oversampled grid K, J taps per axis and the
     trajectory `om` (float32 [M, d] on a HIP device).  Optional `coils`
@@ -60,19 +79,7 @@ class Plan:
         n_arr = (ctypes.c_int64 * d)(*N)
         k_arr = (ctypes.c_int64 * d)(*K)
         self.options = dict(options or {})
-        opt = _lib.PlanOptions()
-        for a, t in enumerate(self.options.get("tile", ())[:3]):
-            opt.tile[a] = int(t)
-        opt.grid_chunk = int(self.options.get("grid_chunk", 0))
-        opt.fft_groups = int(self.options.get("fft_groups", 0))
-        opt.interp_direct = int(bool(self.options.get("interp_direct", 0)))
-        opt.presort = int(self.options.get("presort", 0))
-        opt.fuse_reduce = int(self.options.get("fuse_reduce", 0))
-        opt.grid_mfma = int(self.options.get("grid_mfma", 0))
-        opt.interp_merge = int(self.options.get("interp_merge", 0))
-        interp = self.options.get("interpolator", 0)
-        opt.interpolator = {"kb": 0, "kaiser-bessel": 0, "minmax": 1, "min-max": 1}.get(interp, interp) \
-            if isinstance(interp, str) else int(interp)
+        opt = options_struct(self.options)
         with torch.cuda.device(self.device):
             _lib.call("nufft_plan_ex", d, n_arr, k_arr, self.J, self.M,
                       _ptr(om) if self.M else ctypes.c_void_p(), ctypes.byref(opt), _stream(self.device),
@@ -341,14 +348,19 @@ class Toeplitz:
 
 
 class MultiPlan:
-    """P uneven problems (own N, K, M, trajectory, coils; shared d and J) run
-    together: nufft_multi_forward/adjoint capture all P transform sequences
-    into one HIP graph per set of buffers and replay it with one launch.
+    """P uneven problems (own N, K, M, trajectory, coils, plan options; shared d
+    and J) run together: every stage is one kernel launch over the work blocks
+    of all problems (nufft_multi_forward/adjoint), and the launches of one
+    direction are captured into a HIP graph per set of buffers.
 
     problems: list of dicts with keys om (float32 [M, d] device tensor), N,
-    K (default 2N), coils (complex64 [C, *N] device tensor or None)."""
+    K (default 2N), coils (complex64 [C, *N] device tensor or None) and
+    options (plan options dict, or None).  tune="cache" fills a problem's
+    missing options from the shipped tuning cache (autotune.SHIPPED_CACHE)
+    when it holds an entry for that problem's sizes; tune="off" keeps the
+    built-in defaults."""
 
-    def __init__(self, problems, J: int = 6):
+    def __init__(self, problems, J: int = 6, tune: str = "off"):
         self.device = problems[0]["om"].device
         self.J = int(J)
         self.problems = []
@@ -366,7 +378,12 @@ class MultiPlan:
                 C = int(coils.shape[0])
                 _need(coils, torch.complex64, (C,) + N, "coils", self.device)
             _need(om, torch.float32, (om.shape[0], d), "om", self.device)
-            keep += [om, coils]
+            options = pr.get("options")
+            if options is None and tune == "cache":
+                from . import autotune
+                options = autotune.cached_options(N, K, self.J, int(om.shape[0]), autotune.SHIPPED_CACHE, self.device)
+            opt = options_struct(options) if options else None
+            keep += [om, coils, opt]
             desc = descs[i]
             desc.d, desc.J, desc.M, desc.C = d, self.J, int(om.shape[0]), C
             for a in range(d):
@@ -374,7 +391,8 @@ class MultiPlan:
                 desc.K[a] = K[a]
             desc.om = om.data_ptr() if om.shape[0] else None
             desc.coils = coils.data_ptr() if coils is not None else None
-            self.problems.append(dict(N=N, K=K, M=int(om.shape[0]), C=C, d=d))
+            desc.opt = ctypes.addressof(opt) if opt is not None else None
+            self.problems.append(dict(N=N, K=K, M=int(om.shape[0]), C=C, d=d, options=dict(options or {})))
         self._handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.call("nufft_multi_plan", len(problems), descs, _stream(self.device), ctypes.byref(self._handle))
@@ -390,6 +408,13 @@ class MultiPlan:
             self.close()
         except Exception:
             pass
+
+    def launches(self) -> tuple:
+        """(forward, adjoint) kernel launches per call for the last buffers
+        used in each direction (-1: not called yet)."""
+        f, a = ctypes.c_int64(), ctypes.c_int64()
+        _lib.call("nufft_multi_info", self._handle, ctypes.byref(f), ctypes.byref(a))
+        return f.value, a.value
 
     def yshape(self, p):
         pr = self.problems[p]
