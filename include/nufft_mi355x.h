@@ -308,6 +308,22 @@ int nufft_toeplitz_destroy(nufft_toeplitz_t t);
  * x = A^H (y . w).  Allocates temporary buffers; synchronous on `stream`. */
 int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * iteration and kernels as nufft_density_compensation, with its two complex
+ * [M] sample buffers taken from a static device array of the library instead
+ * of hipMalloc.  Calls no hipMalloc/hipFree and no allocating library
+ * routine; asynchronous on `stream` (no synchronisation).  Limits and errors:
+ * M <= 2^21 samples (the array holds 2 x 2^21 complex64 = 32 MiB per GPU,
+ * kept from the first call on that GPU until the process ends), else
+ * NUFFT_ERR_INVALID_ARG; the plan's own workspace (made by nufft_plan and
+ * nufft_set_points) must exist, else NUFFT_ERR_INVALID_ARG.  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other threads, other plans) race and give wrong weights;
+ * serialise them.  The array keeps the last call's contents; nothing in it
+ * needs to start at zero. */
+int nufft_density_compensation_noalloc(nufft_plan_t plan, int iters, float *w_dev, void *stream);
+
 /* ---- L1TV split-Bregman pieces (Section 2.2, "Iterative NUFFT": the image
  * gradient, Eq. TV, and the L1TV-OLS / L1TV-LAD iterations).  Image-domain
  * kernels, independent of any plan; every array is device complex64 in C

@@ -87,6 +87,7 @@ _SIGS = {
     "nufft_toeplitz_apply": [_vp, ctypes.c_int, _vp, _vp, _vp],
     "nufft_toeplitz_destroy": [_vp],
     "nufft_density_compensation": [_vp, ctypes.c_int, _vp, _vp],
+    "nufft_density_compensation_noalloc": [_vp, ctypes.c_int, _vp, _vp],
     "nufft_tv_shrink": [ctypes.c_int, _i64p, _vp, _vp, _vp, ctypes.c_float, _vp],
     "nufft_tv_rhs": [ctypes.c_int, _i64p, ctypes.c_float, _vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _vp],
     "nufft_tv_normal": [ctypes.c_int, _i64p, ctypes.c_float, _vp, ctypes.c_float, _vp, _vp, _vp],

@@ -2029,6 +2029,23 @@ int nufft_density_compensation(nufft_plan_t plan, int iters, float *w_dev, void 
     return st;
 }
 
+int nufft_density_compensation_noalloc(nufft_plan_t plan, int iters, float *w_dev, void *stream) {
+    int st = dc_check(plan, iters, w_dev, stream);
+    if (st) return st;
+    if (plan->M > kDcScratchMaxM)
+        return fail(NUFFT_ERR_INVALID_ARG,
+                    "M = %lld exceeds the %lld samples of the allocation-free density compensation's scratch",
+                    static_cast<long long>(plan->M), static_cast<long long>(kDcScratchMaxM));
+    if (plan->M == 0 || iters == 0) return NUFFT_OK;
+    // the plan's own workspace (one grid, the partial tiles of the current
+    // binning) must already exist: this call never allocates it
+    if (plan->cap_grids < 1 || plan->n_slots > plan->cap_slots)
+        return fail(NUFFT_ERR_INVALID_ARG, "the plan's workspace is not allocated: call nufft_reserve(plan, 1) first");
+    float2 *wc = nullptr, *u = nullptr;
+    HIP_TRY(dc_scratch(&wc, &u), "look up the device scratch");
+    return dc_iterate(plan, iters, w_dev, wc, u, static_cast<hipStream_t>(stream));
+}
+
 
 // ------------------------------------------------------------ TV split-Bregman pieces
 namespace {

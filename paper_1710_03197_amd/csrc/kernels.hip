@@ -26,6 +26,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <mutex>
 
 #include "nufft_internal.h"
 
@@ -2282,6 +2283,35 @@ hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float s
     if (M == 0) return hipSuccess;
     launch_kernel(k_real_to_complex, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, wc, M, scale);
     return hipGetLastError();
+}
+
+// ---- fixed device scratch of the allocation-free density compensation
+// The two complex sample buffers of the iteration (the weights handed to the
+// gridding, and V V^H of them), kDcScratchMaxM samples each, as one static
+// device array: every GPU the library runs on holds its own copy from the
+// first use until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol); it uses the
+// device address that hipGetSymbolAddress returns, looked up once per device
+// with that device current.
+static __device__ __align__(256) float2 scratch[2 * kDcScratchMaxM];
+
+hipError_t dc_scratch(float2 **wc, float2 **u) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *wc = static_cast<float2 *>(addr[dev]);
+    *u = *wc + kDcScratchMaxM;
+    return hipSuccess;
 }
 
 static TvGeom tv_geom(int d, const int64_t *N) {

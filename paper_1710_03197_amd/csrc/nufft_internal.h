@@ -430,6 +430,11 @@ hipError_t launch_tv_normal(int d, const int64_t *N, float mu, const float2 *aha
 hipError_t launch_bregman_shrink(int64_t n, const float2 *r, float2 *dv, float2 *bv, float t, hipStream_t s);
 hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, float inv_c, hipStream_t s);
 hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s);
+// The allocation-free density compensation's buffers: wc and u, kDcScratchMaxM
+// complex samples each, in a static device array of the current device.
+constexpr int64_t kDcScratchMaxM = int64_t(1) << 21;
+constexpr int kMaxDevices = 64;
+hipError_t dc_scratch(float2 **wc, float2 **u);
 hipError_t launch_permute_points(const float *om, const int *perm, int64_t M, int d, float *om_sorted,
                                  hipStream_t s);
 // Stable sort of (key, value) pairs with hipCUB in caller-owned temporary

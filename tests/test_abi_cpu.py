@@ -104,6 +104,8 @@ def test_new_entry_points_reject_bad_handles():
     assert lib.nufft_toeplitz_plan(vp(), vp(), vp(), ctypes.byref(out)) == -5
     assert lib.nufft_toeplitz_plan(vp(0x10), vp(), vp(), ctypes.byref(out)) == -5
     assert lib.nufft_density_compensation(vp(), 3, vp(), vp()) == -5
+    assert lib.nufft_density_compensation_noalloc(vp(), 3, vp(), vp()) == -5
+    assert lib.nufft_density_compensation_noalloc(vp(0x1234), 3, vp(), vp()) == -5
     assert lib.nufft_grad_points_batched(vp(), 2, vp(), vp(), vp(), vp()) == -5
     assert lib.nufft_set_points(vp(), vp(), vp()) == -5
 
