@@ -94,11 +94,15 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *   fuse_reduce   1: the partial tiles of split gridding tiles are summed by
  *                 the first inverse FFT pass; 2: by a kernel of their own;
  *                 0: the default (1 for d = 2, 2 otherwise; always 2 for d = 1)
- *   grid_mfma     1: gridding on the matrix cores (needs tile[d-1] = 16,
- *                 16, 32 or 64 cells over the leading axes and a tile
- *                 perimeter sum(tile) <= 61, else NUFFT_ERR_UNSUPPORTED);
- *                 2: on the vector ALUs; 0: matrix cores where the tile
- *                 allows it (d >= 2)
+ *   grid_mfma     1: gridding on the matrix cores (d = 3 with tile[2] =
+ *                 16, tile[0], tile[1] in {8, 16} and tile[0] tile[1] <=
+ *                 128: by 4 x 4 blocks of
+ *                 the leading axes; otherwise by row tiles, which need
+ *                 tile[d-1] = 16, 16, 32 or 64 cells over the leading axes
+ *                 and sum(tile) <= 61, else NUFFT_ERR_UNSUPPORTED);
+ *                 2: on the vector ALUs; 3: matrix cores by row tiles
+ *                 also where the block form applies; 0: matrix cores
+ *                 where the tile allows it (d >= 2)
  *   interpolator  0: Kaiser-Bessel (the workloads' kernel); 1: min-max (the
  *                 paper's default, Section 2.1 "Interpolation", after Fessler
  *                 and Sutton): per sample and axis the J coefficients that

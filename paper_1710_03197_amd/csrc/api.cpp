@@ -141,7 +141,8 @@ struct nufft_plan_s {
     int interp_merge = 1;  // tiles along the last axis one gather item may cover
     bool presort = false;      // gridding reads samples permuted into sorted order
     bool fuse_reduce = false;  // first inverse FFT pass sums the partial tiles
-    bool grid_mfma = false;    // gridding on the matrix cores
+    bool grid_mfma = false;    // gridding on the matrix cores by row tiles
+    bool grid_blk = false;     // 3D gridding on the matrix cores by 4 x 4 blocks
     int rec_stride = 0;        // its LDS floats per staged sample
     int seg_len = 16, segs = 1;
     int group_lanes = 64;
@@ -782,6 +783,7 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.item_segs = p->item_segs;
     a.mfma = p->grid_mfma;
     a.rec_stride = p->rec_stride;
+    a.blk = p->grid_blk;
     if (col)
         col->add(kSlotGrid, kStGrid).grid = a;
     else
@@ -1510,6 +1512,15 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
                 }
             if (ls) break;
         }
+        // 3D tiles of 16 cells on the last axis, 8 or 16 on the others and at
+        // most 128 leading cells: the matrix cores by 4 x 4 blocks (default; grid_mfma = 3 asks for the
+        // row-tile matrix-core kernel instead, 2 for the vector ALUs)
+        if (opt && (opt->grid_mfma < 0 || opt->grid_mfma > 3))
+            return bail(fail(NUFFT_ERR_INVALID_ARG, "grid_mfma takes 0, 1, 2 or 3"));
+        const bool blk_ok = d == 3 && L == 16 && (p->T[0] == 8 || p->T[0] == 16) &&
+                            (p->T[1] == 8 || p->T[1] == 16) && p->T[0] * p->T[1] <= 128;
+        p->grid_blk = blk_ok && !(opt && (opt->grid_mfma == 2 || opt->grid_mfma == 3));
+        if (p->grid_blk) ls = 16;
         if (!ls) return bail(fail(NUFFT_ERR_UNSUPPORTED, "no gridding tile shape for this K and J"));
         p->seg_len = ls;
         p->segs = (L + ls - 1) / ls;
@@ -1522,21 +1533,20 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         const int staged = B * Lp + 2 * (B + 1) + (d - 1) * (B + 1) + (d - 1) * J * (B + 1);
         p->stage_floats = std::max(staged, 2 * rows * Lp);
         p->stage_floats = (p->stage_floats + 3) & ~3;  // keep every group's rows 16-byte aligned
-        if (int64_t(256 / p->group_lanes) * p->stage_floats * int64_t(sizeof(float)) > kLdsBudget)
+        if (!p->grid_blk && int64_t(256 / p->group_lanes) * p->stage_floats * int64_t(sizeof(float)) > kLdsBudget)
             return bail(fail(NUFFT_ERR_UNSUPPORTED, "gridding tile too large for LDS"));
-        // matrix-core gridding: tiles of 16 cells on the last axis and 16, 32
-        // or 64 rows (default where the tile allows it)
-        if (opt && (opt->grid_mfma < 0 || opt->grid_mfma > 2))
-            return bail(fail(NUFFT_ERR_INVALID_ARG, "grid_mfma takes 0, 1 or 2"));
+        // matrix-core gridding by row tiles: 16 cells on the last axis and 16,
+        // 32 or 64 rows (default where the tile allows it and the block kernel
+        // does not apply)
         int tsum = 0;
         for (int a = 0; a < d; ++a) tsum += p->T[a];
         p->rec_stride = (2 + tsum) | 1;  // value + the tile's coordinates per axis, odd (no bank conflicts)
         const bool mfma_ok = d >= 2 && L == 16 && (rows == 16 || rows == 32 || rows == 64) &&
                              int64_t(4) * 64 * p->rec_stride * int64_t(sizeof(float)) <= kLdsBudget;
-        if (opt && opt->grid_mfma == 1 && !mfma_ok)
+        if (opt && (opt->grid_mfma == 1 || opt->grid_mfma == 3) && !mfma_ok && !p->grid_blk)
             return bail(fail(NUFFT_ERR_UNSUPPORTED,
                              "matrix-core gridding needs T_last = 16, 16, 32 or 64 rows and sum(T) <= 61"));
-        p->grid_mfma = mfma_ok && !(opt && opt->grid_mfma == 2);
+        p->grid_mfma = !p->grid_blk && mfma_ok && !(opt && opt->grid_mfma == 2);
     }
     {
         int64_t lead = sizeof(float2);

@@ -1514,6 +1514,219 @@ __global__ __launch_bounds__(256) void k_grid_mfma_multi(const GridArgs *__restr
     grid_mfma_body<DIM, NJ, MB>(jobs[b.x], b.y, b.z);
 }
 
+// V^H on the matrix cores in 3D, by blocks.  The tile is T0 x T1 x 16 (T0,
+// T1 in {8, 16}, at most 8 blocks); its leading axes are cut into 4 x 4
+// blocks, and a block with the 16 cells of the last axis is one 16 x 16
+// product over the samples:
+//   H[(x0, x1)][x2] = sum_s (v_s w0_s[x0] w1_s[x1]) w2_s[x2]
+// (v_mfma_f32_16x16x4_f32, samples as the reduction dimension, real and
+// imaginary parts sharing the w2 operand).  Each wavefront stages its own 64
+// samples of a batch (value and per-axis weights spread over the tile's
+// coordinates, out-of-tile taps to a discard slot, and the set of blocks the
+// window reaches) and walks them four at a time over the blocks in
+// registers, running only the products of blocks that one of the four
+// reaches.  Wavefronts synchronise only with themselves until the end, where
+// their tiles are summed in wave order (the result does not depend on
+// scheduling).
+template <int NJ, int T0, int T1>
+__device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, int g) {
+    constexpr int T2 = 16;
+    constexpr int NB1 = T1 / 4;
+    constexpr int NBLK = (T0 / 4) * NB1;
+    constexpr int TRASH = 2;  // discard slot of a record
+    constexpr int ROW[3] = {3, 3 + T0, 3 + T0 + T1};
+    constexpr int TAX[3] = {T0, T1, T2};
+    constexpr int RS = 3 + T0 + T1 + T2;  // floats per record (odd)
+    constexpr int CELLS = T0 * T1 * T2;
+    static_assert(RS % 2 == 1 && NBLK >= 4 && NBLK <= 8, "tile shape");
+    extern __shared__ float blk_lds[];
+    __shared__ int seg_lo[kMaxNeighbors + 1];
+    __shared__ int seg_pre[kMaxNeighbors + 1];
+    const GridItem it = a.items[item];
+    const int nseg = grid_item_segments(a, item, seg_lo, seg_pre);
+    const int J = a.geo.J;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float *rec = blk_lds + wave * 64 * (RS + 1);                 // [64][RS]
+    unsigned *smask = reinterpret_cast<unsigned *>(rec + 64 * RS);  // [64]
+
+    int tc[3];
+    {
+        int t = it.tile;
+#pragma unroll
+        for (int ax = 2; ax >= 0; --ax) {
+            tc[ax] = t % a.nt[ax];
+            t /= a.nt[ax];
+        }
+    }
+    const int base[3] = {tc[0] * T0, tc[1] * T1, tc[2] * T2};
+    const int total = seg_pre[nseg];
+    const int f0 = it.chunk * a.chunk;
+    const int n = min(total, f0 + a.chunk) - f0;
+
+    // walk roles: lane rl + 16 kq reads row rl of sample kq's A operand and
+    // column rl of its B operand; block q covers x0 in 4 (q / NB1) + [0, 4),
+    // x1 in 4 (q % NB1) + [0, 4), its row rl is (x0, x1) = (+rl / 4, +rl % 4)
+    const int rl = lane & 15;
+    const int kq = lane >> 4;
+    const float2 *y = a.y + int64_t(g) * a.M;
+    mfma_f4 acc_re[NBLK], acc_im[NBLK];
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) {
+        acc_re[q] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+        acc_im[q] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    }
+    // trajectory and value of this lane's next sample, loaded one batch ahead
+    float pom[3];
+    float2 pv = make_float2(0.f, 0.f);
+    bool pvalid = false;
+    int cursor = 0;
+    auto fetch = [&](int b) {
+        const int s_idx = b + wave * 64 + lane;
+        pvalid = s_idx < n;
+        const int sg = batch_segment(seg_pre, nseg, cursor, f0 + b + wave * 64, 64, f0 + s_idx);
+        if (pvalid) {
+            const int64_t i = seg_lo[sg] + (f0 + s_idx - seg_pre[sg]);
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) pom[ax] = a.om_sorted[i * 3 + ax];
+            pv = a.y_sorted ? y[i] : y[a.perm[i]];
+        }
+    };
+    fetch(0);
+    for (int b0 = 0; b0 < n; b0 += 256) {
+        {
+            float4 *z = reinterpret_cast<float4 *>(rec);
+            for (int e = lane; e < 16 * RS; e += 64) z[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        group_sync(64);
+        // ---- stage this lane's sample
+        unsigned mk = 0;
+        if (pvalid) {
+            float *my = rec + lane * RS;
+            if (a.geo.minmax) pv = cmulcj(mm_phase<3>(a.geo, pom), pv);
+            my[0] = pv.x;
+            my[1] = pv.y;
+            unsigned bm[2] = {0u, 0u};
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const double u = __dmul_rn(double(pom[ax]), a.geo.C[ax]);
+                const double k0 = floor(u - 0.5 * J) + 1.0;
+                const float fr = float(u - k0 - (0.5 * J - 1.0));
+                const int K = a.geo.K[ax];
+                const int kw = wrap_first_tap(k0, K);
+                float wv[NJ];
+                poly_rows<NJ>(a.geo.coef[ax], a.geo.jp, a.geo.nq[ax], 2.0f * fr - 1.0f, wv);
+                if (a.geo.minmax) mm_sign_taps<NJ>(wv, K - kw);
+                if (a.nt[ax] > 1) {
+                    // first tap relative to the tile, in [-(J-1), T): a window
+                    // wrapping in from the top of the axis comes in negative
+                    int o = kw - base[ax];
+                    if (o >= TAX[ax]) o -= K;
+                    // taps past J carry zero weights (zero coefficient rows)
+                    // and land outside the window: harmless either way
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        const int x = o + j;
+                        my[unsigned(x) < unsigned(TAX[ax]) ? ROW[ax] + x : TRASH] = wv[j];
+                    }
+                    if (ax < 2) {
+                        // blocks of 4 cells the window's cells in the tile fall in
+                        const int c0 = max(o, 0), c1 = min(o + J - 1, TAX[ax] - 1);
+                        bm[ax] = c0 <= c1 ? ((2u << (c1 >> 2)) - 1u) & ~((1u << (c0 >> 2)) - 1u) : 0u;
+                    }
+                } else {
+                    // the axis is one tile: taps wrap around inside it
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        int x = kw + j;
+                        if (x >= K) x -= K;
+                        const bool in = j < J;
+                        my[in ? ROW[ax] + x : TRASH] = wv[j];
+                        if (ax < 2) bm[ax] |= in ? 1u << (x >> 2) : 0u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < T0 / 4; ++b)
+                if ((bm[0] >> b) & 1u) mk |= bm[1] << (b * NB1);
+        }
+        smask[lane] = mk;
+        if (b0 + 256 < n) fetch(b0 + 256);
+        group_sync(64);
+        // ---- walk: lane l < 16 looks at samples 4l .. 4l + 3 (one product's
+        // worth) and the blocks they reach.  Block by block, the wavefront
+        // runs the products with work for that block, two at a time with all
+        // their operand reads issued first (one accumulator per loop, so it
+        // stays in its registers).
+        unsigned gm = 0;
+        if (lane < 16) {
+            const uint4 m4 = reinterpret_cast<const uint4 *>(smask)[lane];
+            gm = m4.x | m4.y | m4.z | m4.w;
+        }
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) {
+            const int a0 = ROW[0] + 4 * (q / NB1) + (rl >> 2);
+            const int a1 = ROW[1] + 4 * (q % NB1) + (rl & 3);
+            uint64_t act = __ballot((gm >> q) & 1u);
+            while (act) {
+                const int g0 = int(__builtin_ctzll(act));
+                act &= act - 1;
+                const bool two = act != 0;
+                const int g1 = two ? int(__builtin_ctzll(act)) : g0;
+                act &= act - 1;
+                const float *s0 = rec + (4 * g0 + kq) * RS;
+                const float *s1 = rec + (4 * g1 + kq) * RS;
+                const float vx0 = s0[0], vy0 = s0[1], b0w = s0[ROW[2] + rl], l0 = s0[a0] * s0[a1];
+                const float vx1 = s1[0], vy1 = s1[1], b1w = s1[ROW[2] + rl], l1 = two ? s1[a0] * s1[a1] : 0.f;
+                acc_re[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx0 * l0, b0w, acc_re[q], 0, 0, 0);
+                acc_im[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy0 * l0, b0w, acc_im[q], 0, 0, 0);
+                acc_re[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx1 * l1, b1w, acc_re[q], 0, 0, 0);
+                acc_im[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy1 * l1, b1w, acc_im[q], 0, 0, 0);
+            }
+        }
+        group_sync(64);
+    }
+    // ---- sum the wavefronts' tiles in wave order and write the tile.  D[i][j]
+    // of block q sits in lane j + 16 (i / 4), register i % 4, block row i being
+    // (x0, x1) = (4 (q / NB1) + i / 4, 4 (q % NB1) + i % 4).
+    __syncthreads();  // every wave is done with its staging area
+    float2 *red = reinterpret_cast<float2 *>(blk_lds);  // [4][CELLS], reuses the staging LDS
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) {
+        const int x0 = 4 * (q / NB1) + kq;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x1 = 4 * (q % NB1) + r;
+            red[wave * CELLS + (x0 * T1 + x1) * T2 + rl] = make_float2(acc_re[q][r], acc_im[q][r]);
+        }
+    }
+    __syncthreads();
+    const bool to_partial = it.nchunks > 1;
+    float2 *dst = to_partial ? a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells
+                             : a.h + int64_t(g) * a.grid_elems;
+    const int64_t K1 = a.geo.K[1], K2 = a.geo.K[2];
+    for (int e = threadIdx.x; e < CELLS; e += 256) {
+        float2 sum = red[e];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) sum = cadd(sum, red[w * CELLS + e]);
+        const int x2 = e % T2, x1 = (e / T2) % T1, x0 = e / (T1 * T2);
+        const int64_t idx = to_partial ? int64_t(e) : (int64_t(base[0] + x0) * K1 + base[1] + x1) * K2 + base[2] + x2;
+        dst[idx] = sum;
+    }
+}
+
+template <int NJ, int T0, int T1>
+__global__ __launch_bounds__(256) void k_grid_blk(GridArgs a) {
+    grid_blk_body<NJ, T0, T1>(a, blockIdx.x, blockIdx.y);
+}
+
+template <int NJ, int T0, int T1>
+__global__ __launch_bounds__(256) void k_grid_blk_multi(const GridArgs *__restrict__ jobs,
+                                                       const int4 *__restrict__ blocks) {
+    const int4 b = blocks[blockIdx.x];
+    grid_blk_body<NJ, T0, T1>(jobs[b.x], b.y, b.z);
+}
+
 // Sums the partial tiles of every split tile in chunk order; one workgroup per
 // (tile, 256 cells, grid).
 __device__ __forceinline__ void reduce_partials_body(const ReduceArgs &a, int64_t hot, int cb, int g) {
@@ -2142,8 +2355,38 @@ hipError_t launch_grid_mfma_d(const GridArgs &a, hipStream_t s) {
     return launch_grid_mfma_j<DIM, 16>(a, s);
 }
 
+template <int NJ, bool MULTI>
+hipError_t launch_grid_blk_j(const GridArgs &a, const GridArgs *jobs, const int4 *blocks, int64_t nblocks,
+                             size_t lds, hipStream_t s) {
+#define NUFFT_BLK_CASE(T0, T1)                                                                               \
+    if (a.T[0] == T0 && a.T[1] == T1) {                                                                      \
+        if (MULTI)                                                                                           \
+            launch_kernel((k_grid_blk_multi<NJ, T0, T1>), dim3(unsigned(nblocks)), dim3(256), lds, s, jobs,  \
+                          blocks);                                                                           \
+        else                                                                                                 \
+            launch_kernel((k_grid_blk<NJ, T0, T1>), dim3(unsigned(a.n_items), unsigned(a.grids)), dim3(256), \
+                          lds, s, a);                                                                        \
+        return hipGetLastError();                                                                            \
+    }
+    NUFFT_BLK_CASE(8, 8)
+    NUFFT_BLK_CASE(8, 16)
+    NUFFT_BLK_CASE(16, 8)
+#undef NUFFT_BLK_CASE
+    return hipErrorInvalidValue;
+}
+
+template <bool MULTI>
+hipError_t launch_grid_blk(const GridArgs &a, const GridArgs *jobs, const int4 *blocks, int64_t nblocks,
+                           size_t lds, hipStream_t s) {
+    if (a.geo.d != 3 || a.T[2] != 16) return hipErrorInvalidValue;
+    if (a.geo.J <= 6) return launch_grid_blk_j<6, MULTI>(a, jobs, blocks, nblocks, lds, s);
+    if (a.geo.J <= 8) return launch_grid_blk_j<8, MULTI>(a, jobs, blocks, nblocks, lds, s);
+    return launch_grid_blk_j<16, MULTI>(a, jobs, blocks, nblocks, lds, s);
+}
+
 hipError_t launch_grid(const GridArgs &a, hipStream_t s) {
     if (a.n_items == 0) return hipSuccess;
+    if (a.blk) return launch_grid_blk<false>(a, nullptr, nullptr, 0, grid_lds(a), s);
     if (a.mfma) {
         switch (a.geo.d) {
             case 2: return launch_grid_mfma_d<2>(a, s);
@@ -2163,6 +2406,13 @@ hipError_t launch_grid(const GridArgs &a, hipStream_t s) {
 // 6/8/16, row blocks) or vector ALUs (d, segment length, coefficient row
 // width), as launch_grid picks it; -1 if there is none.
 int grid_variant(const GridArgs &a) {
+    if (a.blk) {
+        if (a.geo.d != 3 || a.T[2] != 16 || (a.T[0] != 8 && a.T[0] != 16) || (a.T[1] != 8 && a.T[1] != 16) ||
+            a.T[0] * a.T[1] > 128)
+            return -1;
+        const int nj = a.geo.J <= 6 ? 0 : a.geo.J <= 8 ? 1 : 2;
+        return 3000 + 10 * nj + (a.T[0] == 16 ? 2 : 0) + (a.T[1] == 16 ? 1 : 0);
+    }
     if (a.mfma) {
         if (a.geo.d < 2 || a.T[a.geo.d - 1] != 16) return -1;
         const int nj = a.geo.J <= 6 ? 6 : a.geo.J <= 8 ? 8 : 16;
@@ -2176,6 +2426,9 @@ int grid_variant(const GridArgs &a) {
 }
 
 size_t grid_lds(const GridArgs &a) {
+    if (a.blk)
+        return std::max(size_t(256) * (3 + a.T[0] + a.T[1] + a.T[2] + 1) * sizeof(float),
+                        size_t(4) * a.tile_cells * sizeof(float2));
     if (a.mfma) return std::max(size_t(4) * 64 * a.rec_stride, size_t(4) * 2 * a.tile_cells) * sizeof(float);
     return size_t(kGridThreads / a.group_lanes) * a.stage_floats * sizeof(float);
 }
@@ -2228,6 +2481,7 @@ hipError_t launch_grid_multi(const GridArgs *jobs, const int4 *blocks, int64_t n
                              size_t lds, hipStream_t s) {
     if (nblocks == 0) return hipSuccess;
     if (grid_variant(proto) < 0) return hipErrorInvalidValue;
+    if (proto.blk) return launch_grid_blk<true>(proto, jobs, blocks, nblocks, lds, s);
     if (proto.mfma) {
         switch (proto.geo.d) {
             case 2: return grid_mfma_multi_d<2>(jobs, blocks, nblocks, proto, lds, s);

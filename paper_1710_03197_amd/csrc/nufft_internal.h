@@ -234,6 +234,7 @@ struct GridArgs {
                             // sorted sample, offset in the item's list), then (0, total)
     int mfma;             // matrix-core gridding (d >= 2, T_last = 16, 16, 32 or 64 rows)
     int rec_stride;       // its LDS floats per staged sample: 2 + sum of T_a, made odd
+    int blk;              // 3D matrix-core gridding by 4 x 4 blocks (T_2 = 16, T_0 and T_1 in {8, 16})
 };
 
 // Events a timed stage hands to its kernel launch: the launch has the runtime

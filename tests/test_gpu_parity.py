@@ -175,7 +175,7 @@ def test_nonfinite_trajectory_rejected(dev):
 
 
 @pytest.mark.parametrize("opts", [dict(interp_merge=-1), dict(fuse_reduce=3), dict(presort=3), dict(grid_chunk=32),
-                                  dict(fft_groups=-1), dict(grid_mfma=3), dict(interpolator=2)],
+                                  dict(fft_groups=-1), dict(grid_mfma=4), dict(interpolator=2)],
                          ids=["interp_merge", "fuse_reduce", "presort", "grid_chunk", "fft_groups", "grid_mfma",
                               "interpolator"])
 def test_out_of_range_options_rejected(dev, opts):
@@ -317,6 +317,11 @@ OPTION_CASES = [
     ((16, 16, 16), dict(tile=(8, 8, 16), grid_mfma=2)),
     ((16, 16, 16), dict(tile=(8, 8, 16), grid_chunk=64, grid_mfma=1, fuse_reduce=2)),
     ((8, 8, 8), dict(tile=(8, 8, 16), grid_mfma=1)),              # last axis one tile
+    ((16, 16, 16), dict(tile=(8, 8, 16), grid_mfma=3)),            # row tiles where blocks apply
+    ((32, 32, 32), dict(tile=(16, 16, 16), grid_chunk=128)),       # row-tile kernel does not fit: vector ALUs
+    ((32, 32, 32), dict(tile=(16, 8, 16), grid_chunk=256, presort=2)),
+    ((32, 32, 32), dict(tile=(8, 16, 16), fuse_reduce=1)),
+    ((4, 4, 8), dict(tile=(8, 8, 16))),                            # every axis one tile: wrapped windows
     ((64, 64), dict(tile=(16, 16), interp_merge=4)),             # gather items over runs of tiles
     ((16, 16, 16), dict(tile=(8, 8, 8), interp_merge=3)),
     ((64,), dict(tile=(16,), interp_merge=5)),
