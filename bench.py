@@ -11,8 +11,16 @@ oracle at relative L2 <= 1e-5.  Prints one JSON line with pairs/s, the
 roofline of the dominant kernel (per-kernel HIP events recorded by the
 library on the launch stream, in a second loop identical to the timed one),
 the FP64 oracle timed on the host cores, and extra fields for the 3D 128^3
-koosh-ball pair and for the uneven multi-problem batch (24 spiral problems x 8
-coils in one graph launch) versus looped single transforms.
+koosh-ball pair, for the uneven multi-problem batch (24 spiral problems x 8
+coils, one launch per stage) versus looped single transforms, for the
+achievable device-to-device copy bandwidth, for the dispatch floor of a
+six-kernel sequence (eager and graph-replayed), and for the method's own
+NUFFT-versus-NUDFT error (the FP64 oracle against the direct sum at the
+64x64 / 4096-sample configuration).
+
+The oracle (test infrastructure) is used only in the CPU-baseline leg: its
+timing, and its reference outputs for the parity gates and the NUDFT error.
+`--workloads` picks the parts to run (profiling runs use one at a time).
 """
 from __future__ import annotations
 
@@ -346,6 +354,94 @@ def bench_batched(dev, steps, warmup, orc_mod, n_problems=24):
                 ms_per_batch_batched=round(res["batched"] * 1e3, 3), rel_err=max(errs))
 
 
+def stream_copy(dev, mib=1024, reps=20):
+    """Achievable HBM bandwidth: a device-to-device copy of `mib` MiB (read
+    and write counted), best of `reps` event-timed copies."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(reps + 2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    gbs = 2 * n * 4 / (best * 1e-3) / 1e9
+    del src, dst
+    return {"gb_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_moved": 2 * n * 4,
+            "kind": "torch device-to-device copy, best of %d" % reps}
+
+
+def dispatch_floor(dev, n_launch=6, steps=2000):
+    """Time of a sequence of `n_launch` one-workgroup kernels (the pair's
+    launch count in 2D), back to back on one stream, eager and as a replayed
+    HIP graph: the floor under which the 2D pair cannot go."""
+    import torch
+    bufs = [torch.zeros(64, device=dev) for _ in range(n_launch)]
+
+    def seq():
+        for b in bufs:
+            b.add_(1.0)
+
+    out = {}
+    for _ in range(20):
+        seq()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        seq()
+    torch.cuda.synchronize()
+    out["eager_us"] = round((time.perf_counter() - t0) / steps * 1e6, 2)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        seq()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        seq()
+    for _ in range(20):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    out["graph_us"] = round((time.perf_counter() - t0) / steps * 1e6, 2)
+    out["launches"] = n_launch
+    return out
+
+
+def nudft_error(orc_mod):
+    """The method's approximation error at J = 6, sigma = 2: the FP64 oracle
+    (which follows the NUFFT pipeline) against the direct non-uniform DFT
+    y_m = sum_n x_n exp(-i omega_m . n), n centred, on the 64x64 image with 32
+    radial spokes x 128 readout points."""
+    import numpy as np
+    from paper_1710_03197_amd import data
+    c = data.config1()
+    N, K, J, om, x = c["N"], c["K"], c["J"], c["om"], c["x"]
+    grids = np.meshgrid(*[np.arange(n) - n // 2 for n in N], indexing="ij")
+    pts = np.stack([g.ravel() for g in grids], 1).astype(np.float64)
+    y = np.exp(-1j * (om.astype(np.float64) @ pts.T)) @ x.astype(np.complex128).ravel()
+    return {"rel_l2": rel_l2(orc_mod.forward(x, om, N, K, J), y), "workload": "64x64, grid 128x128, J=6, M=4096"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(orc_mod, budget_s=12.0):
     """The FP64 oracle pair on the 2D workload, repeated for about budget_s."""
     from paper_1710_03197_amd import data
@@ -362,7 +458,8 @@ def cpu_baseline(orc_mod, budget_s=12.0):
     sec = (time.perf_counter() - t0) / reps
     return {"value": round(1.0 / sec, 3), "unit": "pairs/s", "cores": orc_mod.num_threads(), "kind": "oracle",
             "sample": f"{reps} full FP64 forward+adjoint pairs of the 2D 256^2 workload (M=131072), "
-                      f"{sec * 1e3:.1f} ms each"}
+                      f"{sec * 1e3:.1f} ms each",
+            "cpu_model": cpu_model(), "omp_proc_bind": os.environ.get("OMP_PROC_BIND")}
 
 
 def main():
@@ -370,6 +467,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workloads", default="2d,3d,batched",
+                    help="comma-separated parts to run: 2d (the headline value), 3d, batched")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--tune", choices=["cache", "now", "off"], default="cache",
@@ -386,6 +485,14 @@ def main():
               file=sys.stderr)
         raise SystemExit(2)
 
+    parts = {w.strip() for w in args.workloads.split(",") if w.strip()}
+    if args.no_3d:
+        parts.discard("3d")
+    if args.no_batched:
+        parts.discard("batched")
+    # the FP64 oracle's OpenMP threads stay on adjacent cores (set before the
+    # oracle library starts its runtime)
+    os.environ.setdefault("OMP_PROC_BIND", "close")
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
@@ -393,20 +500,24 @@ def main():
     dev = torch.device("cuda:0")
     khash = kernels_hash()
 
-    r2 = bench_2d(dev, args.steps, args.warmup, orc_mod, tune=args.tune, no_graph=args.no_graph)
-    dom, roof = roofline_entry(r2["ktimes"], r2["alg"], khash, "2d_256_golden_radial",
-                               (r2["tuned"] or {}).get("options"))
-    extra = {
-        "rel_err_forward": r2["err_f"], "rel_err_adjoint": r2["err_a"],
-        "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r2["ktimes"].items()},
-        "graph_replay_pairs_per_s": None if r2["sec_graph"] is None else round(1.0 / r2["sec_graph"], 2),
-        "pair_bytes_model": int(sum(r2["alg"].values())),
-        "pair_model_frac": round(sum(r2["alg"].values()) / r2["sec"] / 1e9 / HBM_PEAK_GBS, 4),
-        "plan": r2["info"], "kernels_sha": khash, "tuning": r2["tuned"],
-        "toeplitz_normal_2d": r2["toeplitz"],
-        "minmax_interpolator_2d": r2["minmax"],
-    }
-    if not args.no_3d:
+    r2, roof = None, None
+    extra = {"kernels_sha": khash}
+    if "2d" in parts:
+        r2 = bench_2d(dev, args.steps, args.warmup, orc_mod, tune=args.tune, no_graph=args.no_graph)
+        dom, roof = roofline_entry(r2["ktimes"], r2["alg"], khash, "2d_256_golden_radial",
+                                   (r2["tuned"] or {}).get("options"))
+        extra.update({
+            "rel_err_forward": r2["err_f"], "rel_err_adjoint": r2["err_a"],
+            "kernels_us_per_pair": {k: round(n * ms * 1e3, 2) for k, (n, ms) in r2["ktimes"].items()},
+            "graph_replay_pairs_per_s": None if r2["sec_graph"] is None else round(1.0 / r2["sec_graph"], 2),
+            "pair_bytes_model": int(sum(r2["alg"].values())),
+            "pair_model_frac": round(sum(r2["alg"].values()) / r2["sec"] / 1e9 / HBM_PEAK_GBS, 4),
+            "plan": r2["info"], "tuning": r2["tuned"],
+            "toeplitz_normal_2d": r2["toeplitz"],
+            "minmax_interpolator_2d": r2["minmax"],
+            "dispatch_floor_6_launches": dispatch_floor(dev),
+        })
+    if "3d" in parts:
         r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod, tune=args.tune)
         _, roof3 = roofline_entry(r3["ktimes"], r3["alg"], khash, "3d_128_koosh", (r3["tuned"] or {}).get("options"))
         extra["3d_128"] = {
@@ -419,9 +530,13 @@ def main():
             "tuning": r3["tuned"],
             "toeplitz_normal": r3["toeplitz"],
         }
-    if not args.no_batched:
+    if "batched" in parts:
         extra["batched_vs_looped"] = bench_batched(dev, max(3, args.steps // 40), 2, orc_mod)
-    cpu = None if args.no_cpu else cpu_baseline(orc_mod, args.cpu_seconds)
+    extra["stream_copy"] = stream_copy(dev)
+    cpu = None
+    if not args.no_cpu and r2 is not None:
+        cpu = cpu_baseline(orc_mod, args.cpu_seconds)
+        extra["nufft_vs_nudft"] = nudft_error(orc_mod)
     if args.calibration_copy_mb > 0:
         n = args.calibration_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -433,12 +548,12 @@ def main():
 
     result = {
         "metric": METRIC,
-        "value": round(1.0 / r2["sec"], 2),
+        "value": None if r2 is None else round(1.0 / r2["sec"], 2),
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r2["sec"] * 1e3, 4),
+        "ms_per_step": None if r2 is None else round(r2["sec"] * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
