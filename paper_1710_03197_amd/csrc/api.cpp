@@ -784,6 +784,11 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.mfma = p->grid_mfma;
     a.rec_stride = p->rec_stride;
     a.blk = p->grid_blk;
+    {
+        int tsum = 0;
+        for (int ax = 0; ax < p->d; ++ax) tsum += p->T[ax];
+        a.grids_per_wg = p->grid_mfma ? grid_grids_per_wg(grids, p->tile_cells, tsum) : 1;
+    }
     if (col)
         col->add(kSlotGrid, kStGrid).grid = a;
     else
@@ -938,7 +943,8 @@ void stage_blocks(const Emitted &em, int job, int threads, std::vector<int4> &ou
         }
         case kStGrid: {
             const GridArgs &a = em.grid;
-            for (int g = 0; g < a.grids; ++g)
+            const int gp = a.mfma ? a.grids_per_wg : 1;
+            for (int g = 0; g < (a.grids + gp - 1) / gp; ++g)
                 for (int64_t b = 0; b < a.n_items; ++b) out.push_back(make_int4(job, int(b), g, 0));
             break;
         }

@@ -1326,15 +1326,17 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_multi(const GridArgs *__r
 // a product of a rows x samples matrix and a samples x 16 matrix, i.e.
 // 16x16x4 fp32 MFMAs with the samples as the reduction dimension (real and
 // imaginary parts as two products sharing the wlast operand).  Each wave
-// stages 64 samples in LDS: the value and, per axis, the sample's weights
-// spread over the tile's T_a coordinates (zero outside the window, window
-// wrapping resolved here), so in the walk lane (i + 16k) reads A[i][k] and
-// B[k][i] of sample k at fixed offsets.  The four waves take different samples
-// of the item and their tiles are summed in LDS in wave order (deterministic).
+// stages 64 samples in LDS: the values of the GP grids the workgroup grids
+// (coils or batch entries share the trajectory, so the window weights are
+// staged once for all of them) and, per axis, the sample's weights spread
+// over the tile's T_a coordinates (zero outside the window, window wrapping
+// resolved here), so in the walk lane (i + 16k) reads A[i][k] and B[k][i] of
+// sample k at fixed offsets.  The four waves take different samples of the
+// item and their tiles are summed in LDS in wave order (deterministic).
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
-template <int DIM, int NJ, int MB>
-__device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, int g) {
+template <int DIM, int NJ, int MB, int GP>
+__device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, int gg) {
     extern __shared__ float mf_lds[];
     __shared__ int seg_lo[kMaxNeighbors + 1];
     __shared__ int seg_pre[kMaxNeighbors + 1];
@@ -1343,7 +1345,12 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
     const int J = a.geo.J;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
     const int lane = threadIdx.x & 63;
-    const int RS = a.rec_stride;  // floats per staged sample: v.x, v.y, then T_a weights per axis
+    const int g0 = gg * GP;                        // first grid of this workgroup
+    const int ng = min(GP, a.grids - g0);          // grids it writes
+    int tsum = 0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) tsum += a.T[ax];
+    const int RS = (2 * GP + tsum) | 1;  // floats per staged sample: GP values, then T_a weights per axis (odd)
     float *rec = mf_lds + wave * 64 * RS;
 
     int tc[DIM];
@@ -1360,7 +1367,7 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
     const int n = min(total, f0 + a.chunk) - f0;
     int base[DIM], off[DIM];
     {
-        int o = 2;
+        int o = 2 * GP;
 #pragma unroll
         for (int ax = 0; ax < DIM; ++ax) {
             base[ax] = tc[ax] * a.T[ax];
@@ -1384,17 +1391,19 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
         }
     }
     const int boff = off[DIM - 1] + rl;
-    const float2 *y = a.y + int64_t(g) * a.M;
-    mfma_f4 acc_re[MB], acc_im[MB];
+    mfma_f4 acc_re[GP][MB], acc_im[GP][MB];
 #pragma unroll
-    for (int blk = 0; blk < MB; ++blk) {
-        acc_re[blk] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-        acc_im[blk] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < GP; ++q) {
+#pragma unroll
+        for (int blk = 0; blk < MB; ++blk) {
+            acc_re[q][blk] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+            acc_im[q][blk] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+        }
     }
-    // The global reads of a batch (trajectory, sample value) are issued one
+    // The global reads of a batch (trajectory, sample values) are issued one
     // batch ahead, so they are in flight while the wave walks the current one.
     float pom[DIM];
-    float2 pv = make_float2(0.f, 0.f);
+    float2 pv[GP];
     bool pvalid = false;
     int cursor = 0;
     auto fetch = [&](int b) {
@@ -1406,16 +1415,26 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
             const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
 #pragma unroll
             for (int ax = 0; ax < DIM; ++ax) pom[ax] = a.om_sorted[i * DIM + ax];
-            pv = a.y_sorted ? y[i] : y[a.perm[i]];
+            const int64_t src = a.y_sorted ? i : int64_t(a.perm[i]);
+#pragma unroll
+            for (int q = 0; q < GP; ++q)
+                pv[q] = q < ng ? a.y[int64_t(g0 + q) * a.M + src] : make_float2(0.f, 0.f);
         }
     };
     fetch(0);
     for (int b0 = 0; b0 < n; b0 += 256) {
         // ---- stage: lane = sample b0 + 64 * wave + lane of the item
         float *my = rec + lane * RS;
-        if (pvalid && a.geo.minmax) pv = cmulcj(mm_phase<DIM>(a.geo, pom), pv);
-        my[0] = pvalid ? pv.x : 0.f;
-        my[1] = pvalid ? pv.y : 0.f;
+        {
+            float2 ph = make_float2(1.f, 0.f);
+            if (pvalid && a.geo.minmax) ph = mm_phase<DIM>(a.geo, pom);
+#pragma unroll
+            for (int q = 0; q < GP; ++q) {
+                const float2 v = pvalid ? (a.geo.minmax ? cmulcj(ph, pv[q]) : pv[q]) : make_float2(0.f, 0.f);
+                my[2 * q] = v.x;
+                my[2 * q + 1] = v.y;
+            }
+        }
 #pragma unroll
         for (int ax = 0; ax < DIM; ++ax) {
             float *E = my + off[ax];
@@ -1449,69 +1468,83 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
 #pragma unroll 2
         for (int st = 0; st * 4 < nb; ++st) {
             const float *sr = rec + (st * 4 + kq) * RS;
-            const float vx = sr[0], vy = sr[1];
+            float vx[GP], vy[GP];
+#pragma unroll
+            for (int q = 0; q < GP; ++q) {
+                vx[q] = sr[2 * q];
+                vy[q] = sr[2 * q + 1];
+            }
             const float bw = sr[boff];
 #pragma unroll
             for (int blk = 0; blk < MB; ++blk) {
                 float wl = sr[aoff[blk][0]];
 #pragma unroll
                 for (int ax = 1; ax < DIM - 1; ++ax) wl *= sr[aoff[blk][ax]];
-                acc_re[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx * wl, bw, acc_re[blk], 0, 0, 0);
-                acc_im[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy * wl, bw, acc_im[blk], 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < GP; ++q) {
+                    acc_re[q][blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx[q] * wl, bw, acc_re[q][blk], 0, 0, 0);
+                    acc_im[q][blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy[q] * wl, bw, acc_im[q][blk], 0, 0, 0);
+                }
             }
         }
         group_sync(64);
     }
-    // ---- sum the waves' tiles in wave order and write the tile
-    __syncthreads();  // every wave is done with its staging area
+    // ---- per grid: sum the waves' tiles in wave order and write the tile
     const int cells = MB * 256;
     float2 *red = reinterpret_cast<float2 *>(mf_lds);  // [4][cells], reuses the staging LDS
 #pragma unroll
-    for (int blk = 0; blk < MB; ++blk) {
+    for (int q = 0; q < GP; ++q) {
+        __syncthreads();  // every wave is done with the staging area / the previous grid's sums
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = blk * 16 + 4 * kq + q;  // D[row][col] sits in lane col + 16 (row / 4), register row % 4
-            red[wave * cells + row * 16 + rl] = make_float2(acc_re[blk][q], acc_im[blk][q]);
-        }
-    }
-    __syncthreads();
-    const bool to_partial = it.nchunks > 1;
-    float2 *dst = to_partial ? a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells
-                             : a.h + int64_t(g) * a.grid_elems;
-    for (int e = threadIdx.x; e < cells; e += 256) {
-        float2 sum = red[e];
+        for (int blk = 0; blk < MB; ++blk) {
 #pragma unroll
-        for (int q = 1; q < 4; ++q) sum = cadd(sum, red[q * cells + e]);
-        int64_t idx;
-        if (to_partial) {
-            idx = e;
-        } else {
-            int rr = e >> 4;
-            int l[DIM];
-            l[DIM - 1] = e & 15;
-#pragma unroll
-            for (int ax = DIM - 2; ax >= 0; --ax) {
-                l[ax] = rr % a.T[ax];
-                rr /= a.T[ax];
+            for (int r = 0; r < 4; ++r) {
+                const int row = blk * 16 + 4 * kq + r;  // D[row][col] sits in lane col + 16 (row / 4), register row % 4
+                red[wave * cells + row * 16 + rl] = make_float2(acc_re[q][blk][r], acc_im[q][blk][r]);
             }
-            idx = 0;
-#pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) idx = idx * a.geo.K[ax] + base[ax] + l[ax];
         }
-        dst[idx] = sum;
+        __syncthreads();
+        if (q < ng) {
+            const int g = g0 + q;
+            const bool to_partial = it.nchunks > 1;
+            float2 *dst = to_partial ? a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells
+                                     : a.h + int64_t(g) * a.grid_elems;
+            for (int e = threadIdx.x; e < cells; e += 256) {
+                float2 sum = red[e];
+#pragma unroll
+                for (int w = 1; w < 4; ++w) sum = cadd(sum, red[w * cells + e]);
+                int64_t idx;
+                if (to_partial) {
+                    idx = e;
+                } else {
+                    int rr = e >> 4;
+                    int l[DIM];
+                    l[DIM - 1] = e & 15;
+#pragma unroll
+                    for (int ax = DIM - 2; ax >= 0; --ax) {
+                        l[ax] = rr % a.T[ax];
+                        rr /= a.T[ax];
+                    }
+                    idx = 0;
+#pragma unroll
+                    for (int ax = 0; ax < DIM; ++ax) idx = idx * a.geo.K[ax] + base[ax] + l[ax];
+                }
+                dst[idx] = sum;
+            }
+        }
     }
 }
 
-template <int DIM, int NJ, int MB>
+template <int DIM, int NJ, int MB, int GP>
 __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
-    grid_mfma_body<DIM, NJ, MB>(a, blockIdx.x, blockIdx.y);
+    grid_mfma_body<DIM, NJ, MB, GP>(a, blockIdx.x, blockIdx.y);
 }
 
-template <int DIM, int NJ, int MB>
+template <int DIM, int NJ, int MB, int GP>
 __global__ __launch_bounds__(256) void k_grid_mfma_multi(const GridArgs *__restrict__ jobs,
                                                         const int4 *__restrict__ blocks) {
     const int4 b = blocks[blockIdx.x];
-    grid_mfma_body<DIM, NJ, MB>(jobs[b.x], b.y, b.z);
+    grid_mfma_body<DIM, NJ, MB, GP>(jobs[b.x], b.y, b.z);
 }
 
 // V^H on the matrix cores in 3D, by blocks.  The tile is T0 x T1 x 16 (T0,
@@ -2332,18 +2365,33 @@ hipError_t launch_grid_d(const GridArgs &a, hipStream_t s) {
     }
 }
 
-template <int DIM, int NJ>
-hipError_t launch_grid_mfma_j(const GridArgs &a, hipStream_t s) {
-    const int cells = a.tile_cells;
+template <int DIM, int NJ, int MB>
+hipError_t launch_grid_mfma_m(const GridArgs &a, hipStream_t s) {
     const size_t lds = grid_lds(a);
-    const dim3 grid(unsigned(a.n_items), unsigned(a.grids));
-    switch (cells) {
-        case 256: launch_kernel((k_grid_mfma<DIM, NJ, 1>), grid, dim3(256), lds, s, a); break;
-        case 512: launch_kernel((k_grid_mfma<DIM, NJ, 2>), grid, dim3(256), lds, s, a); break;
-        case 1024: launch_kernel((k_grid_mfma<DIM, NJ, 4>), grid, dim3(256), lds, s, a); break;
+    const int gp = a.grids_per_wg;
+    const dim3 grid(unsigned(a.n_items), unsigned((a.grids + gp - 1) / gp));
+    switch (gp) {
+        case 1: launch_kernel((k_grid_mfma<DIM, NJ, MB, 1>), grid, dim3(256), lds, s, a); break;
+        case 2: launch_kernel((k_grid_mfma<DIM, NJ, MB, 2>), grid, dim3(256), lds, s, a); break;
+        case 4:
+            if constexpr (MB <= 2) {
+                launch_kernel((k_grid_mfma<DIM, NJ, MB, 4>), grid, dim3(256), lds, s, a);
+                break;
+            }
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int DIM, int NJ>
+hipError_t launch_grid_mfma_j(const GridArgs &a, hipStream_t s) {
+    switch (a.tile_cells) {
+        case 256: return launch_grid_mfma_m<DIM, NJ, 1>(a, s);
+        case 512: return launch_grid_mfma_m<DIM, NJ, 2>(a, s);
+        case 1024: return launch_grid_mfma_m<DIM, NJ, 4>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int DIM>
@@ -2418,7 +2466,9 @@ int grid_variant(const GridArgs &a) {
         const int nj = a.geo.J <= 6 ? 6 : a.geo.J <= 8 ? 8 : 16;
         const int mb = a.tile_cells / 256;
         if (a.tile_cells % 256 || (mb != 1 && mb != 2 && mb != 4)) return -1;
-        return 1000 + 100 * a.geo.d + 10 * (nj == 6 ? 0 : nj == 8 ? 1 : 2) + mb;
+        const int gp = a.grids_per_wg;
+        if ((gp != 1 && gp != 2 && gp != 4) || gp * mb > 8) return -1;
+        return 10000 * gp + 1000 + 100 * a.geo.d + 10 * (nj == 6 ? 0 : nj == 8 ? 1 : 2) + mb;
     }
     if (a.seg_len != 4 && a.seg_len != 8 && a.seg_len != 16) return -1;
     if (a.geo.jp != 8 && a.geo.jp != 16) return -1;
@@ -2429,29 +2479,50 @@ size_t grid_lds(const GridArgs &a) {
     if (a.blk)
         return std::max(size_t(256) * (3 + a.T[0] + a.T[1] + a.T[2] + 1) * sizeof(float),
                         size_t(4) * a.tile_cells * sizeof(float2));
-    if (a.mfma) return std::max(size_t(4) * 64 * a.rec_stride, size_t(4) * 2 * a.tile_cells) * sizeof(float);
+    if (a.mfma) {
+        int tsum = 0;
+        for (int ax = 0; ax < a.geo.d; ++ax) tsum += a.T[ax];
+        const size_t rs = size_t((2 * a.grids_per_wg + tsum) | 1);
+        return std::max(size_t(4) * 64 * rs, size_t(4) * 2 * a.tile_cells) * sizeof(float);
+    }
     return size_t(kGridThreads / a.group_lanes) * a.stage_floats * sizeof(float);
 }
 
 namespace {
-template <int DIM, int NJ>
-hipError_t grid_mfma_multi_j(const GridArgs *jobs, const int4 *blocks, int64_t n, int mb, size_t lds, hipStream_t s) {
-    switch (mb) {
-        case 1: launch_kernel((k_grid_mfma_multi<DIM, NJ, 1>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
-        case 2: launch_kernel((k_grid_mfma_multi<DIM, NJ, 2>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
-        case 4: launch_kernel((k_grid_mfma_multi<DIM, NJ, 4>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
+template <int DIM, int NJ, int MB>
+hipError_t grid_mfma_multi_m(const GridArgs *jobs, const int4 *blocks, int64_t n, int gp, size_t lds, hipStream_t s) {
+    switch (gp) {
+        case 1: launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 1>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
+        case 2: launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 2>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
+        case 4:
+            if constexpr (MB <= 2) {
+                launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 4>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks);
+                break;
+            }
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int DIM, int NJ>
+hipError_t grid_mfma_multi_j(const GridArgs *jobs, const int4 *blocks, int64_t n, int mb, int gp, size_t lds,
+                             hipStream_t s) {
+    switch (mb) {
+        case 1: return grid_mfma_multi_m<DIM, NJ, 1>(jobs, blocks, n, gp, lds, s);
+        case 2: return grid_mfma_multi_m<DIM, NJ, 2>(jobs, blocks, n, gp, lds, s);
+        case 4: return grid_mfma_multi_m<DIM, NJ, 4>(jobs, blocks, n, gp, lds, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int DIM>
 hipError_t grid_mfma_multi_d(const GridArgs *jobs, const int4 *blocks, int64_t n, const GridArgs &p, size_t lds,
                              hipStream_t s) {
     const int mb = p.tile_cells / 256;
-    if (p.geo.J <= 6) return grid_mfma_multi_j<DIM, 6>(jobs, blocks, n, mb, lds, s);
-    if (p.geo.J <= 8) return grid_mfma_multi_j<DIM, 8>(jobs, blocks, n, mb, lds, s);
-    return grid_mfma_multi_j<DIM, 16>(jobs, blocks, n, mb, lds, s);
+    if (p.geo.J <= 6) return grid_mfma_multi_j<DIM, 6>(jobs, blocks, n, mb, p.grids_per_wg, lds, s);
+    if (p.geo.J <= 8) return grid_mfma_multi_j<DIM, 8>(jobs, blocks, n, mb, p.grids_per_wg, lds, s);
+    return grid_mfma_multi_j<DIM, 16>(jobs, blocks, n, mb, p.grids_per_wg, lds, s);
 }
 
 template <int DIM, int LS>

@@ -235,7 +235,20 @@ struct GridArgs {
     int mfma;             // matrix-core gridding (d >= 2, T_last = 16, 16, 32 or 64 rows)
     int rec_stride;       // its LDS floats per staged sample: 2 + sum of T_a, made odd
     int blk;              // 3D matrix-core gridding by 4 x 4 blocks (T_2 = 16, T_0 and T_1 in {8, 16})
+    int grids_per_wg;     // row-tile matrix-core gridding: grids one workgroup grids together (1, 2, 4)
 };
+// Grids per workgroup of the row-tile matrix-core gridding: the window weights
+// are staged once for all of them (coils and batch entries share the
+// trajectory); four at most, at most eight accumulator blocks per lane, and
+// the staged records (2 floats per grid + the tile's edge lengths tsum, odd)
+// of four wavefronts within 64 KiB.
+inline int grid_grids_per_wg(int grids, int tile_cells, int tsum) {
+    const int mb = tile_cells / 256;
+    auto fits = [&](int gp) { return gp * mb <= 8 && 4 * 64 * ((2 * gp + tsum) | 1) * 4 <= 64 * 1024; };
+    if (grids >= 3 && fits(4)) return 4;
+    if (grids >= 2 && fits(2)) return 2;
+    return 1;
+}
 
 // Events a timed stage hands to its kernel launch: the launch has the runtime
 // stamp them at the kernel's own start and end (hipExtLaunchKernel), so the
