@@ -111,6 +111,15 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *                 Kaiser-Bessel transform (the same J and beta).  With
  *                 min-max, nufft_grad_points and nufft_density_compensation
  *                 return NUFFT_ERR_UNSUPPORTED.
+ *   weight_table  1: the plan stores every sample's interpolation window
+ *                 (first taps and the J weights per axis, made with the
+ *                 binning: M * 4 * (2 + d * J') bytes rounded up to 16 per
+ *                 sample, J' = J rounded up to 6, 8 or 16), and the
+ *                 gridding and the staged interpolation read it instead of
+ *                 evaluating the kernel per sample (the paper's precomputed
+ *                 interpolator, Section 2.1 "Interpolation"); Kaiser-Bessel
+ *                 only (with min-max: NUFFT_ERR_UNSUPPORTED); 0: evaluate on
+ *                 the fly
  *   interp_merge  most grid tiles along the last axis that one interpolation
  *                 work item covers when their samples are few (>= 1; the
  *                 region it stages must fit 64 KiB of LDS, wider runs are
@@ -127,7 +136,7 @@ typedef struct {
     int grid_mfma;
     int interpolator;
     int interp_merge;
-    int reserved[1];
+    int weight_table;
 } nufft_options_t;
 
 /* nufft_plan with tuning options (opt may be NULL = defaults). */

@@ -159,6 +159,11 @@ struct nufft_plan_s {
     void *sort_temp = nullptr;
     size_t sort_temp_bytes = 0;
     float *om_prev = nullptr;  // the trajectory in force while a new one is binned
+    // per sorted sample its window (first taps and weights), made with the
+    // binning when the plan asks for it (option weight_table), else nullptr
+    bool use_wtab = false;
+    float *wtab = nullptr;
+    size_t cap_wtab = 0;  // floats
     // coils
     float2 *coils = nullptr;
     int C = 1;
@@ -194,6 +199,8 @@ struct nufft_plan_s {
             g.coef[a] = coef[a];
             g.dcoef[a] = dcoef[a];
         }
+        g.wtab = use_wtab ? wtab : nullptr;
+        g.wtab_stride = use_wtab ? table_stride(d, J) : 0;
         return g;
     }
 };
@@ -274,6 +281,7 @@ void free_plan(nufft_plan_s *p) {
     if (p->sort_temp) (void)hipFree(p->sort_temp);
     p->sort_temp = nullptr;
     dfree(p->om_prev);
+    dfree(p->wtab);
     dfree(p->om);
     dfree(p->om_sorted);
     dfree(p->perm);
@@ -352,6 +360,18 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
                             s)) != hipSuccess)
             break;
         if ((e = launch_permute_points(p->om, p->perm, M, d, p->om_sorted, s)) != hipSuccess) break;
+        if (p->use_wtab) {
+            // the window table: allocated once for the plan's M (a re-bin
+            // rewrites it in place)
+            const size_t need = size_t(std::max<int64_t>(M, 1)) * size_t(table_stride(d, p->J));
+            if (need > p->cap_wtab) {
+                dfree(p->wtab);
+                p->cap_wtab = 0;
+                if ((e = dmalloc(&p->wtab, need)) != hipSuccess) break;
+                p->cap_wtab = need;
+            }
+            if ((e = launch_weight_table(p->geom(), p->om_sorted, M, p->wtab, s)) != hipSuccess) break;
+        }
         if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
     } while (false);
     if (e != hipSuccess) return hip_fail(e, "binning the trajectory");
@@ -1478,6 +1498,11 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     if (opt && (opt->interpolator < 0 || opt->interpolator > 1))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "interpolator takes 0 (Kaiser-Bessel) or 1 (min-max)"));
     p->minmax = opt && opt->interpolator == 1;
+    if (opt && (opt->weight_table < 0 || opt->weight_table > 1))
+        return bail(fail(NUFFT_ERR_INVALID_ARG, "weight_table takes 0 or 1"));
+    p->use_wtab = opt && opt->weight_table == 1;
+    if (p->use_wtab && p->minmax)
+        return bail(fail(NUFFT_ERR_UNSUPPORTED, "the window table holds Kaiser-Bessel weights only"));
     for (int a = 0; a < d; ++a) {
         const double beta = kb_beta(J, double(K[a]) / double(N[a]));
         if (p->minmax ? !minmax_fit(int(N[a]), int(K[a]), J, beta, &p->ker[a]) : !kb_fit(J, beta, &p->ker[a]))
@@ -1799,8 +1824,10 @@ int nufft_plan_info(nufft_plan_t plan, double *beta3, int *poly_degree, int *til
     if (n_items) *n_items = plan->n_items;
     if (workspace_bytes)
         *workspace_bytes = int64_t(plan->cap_grids) *
-                           (plan->grid_elems + plan->tmp_elems + std::max<int64_t>(plan->n_slots, 1) * plan->tile_cells) *
-                           int64_t(sizeof(float2));
+                               (plan->grid_elems + plan->tmp_elems +
+                                std::max<int64_t>(plan->n_slots, 1) * plan->tile_cells) *
+                               int64_t(sizeof(float2)) +
+                           int64_t(plan->cap_wtab) * int64_t(sizeof(float));
     return NUFFT_OK;
 }
 

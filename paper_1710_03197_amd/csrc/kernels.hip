@@ -828,6 +828,75 @@ __device__ __forceinline__ void window_weights(const SampleGeom &geo, const floa
     poly_rows<J>(rows, geo.jp, nq, 2.0f * f - 1.0f, w);
 }
 
+// ---- the plan's window table (optional): one record per sorted sample
+constexpr int table_taps_c(int J) { return J <= 6 ? 6 : J <= 8 ? 8 : 16; }
+constexpr int table_f4(int DIM, int NJ) { return (2 + DIM * NJ + 3) / 4; }
+
+// Window of sorted sample i on every axis: wrapped first taps and the NJ
+// weights (zero past J), evaluated exactly as the table records them.
+template <int NJ, int DIM>
+__device__ __forceinline__ void eval_window(const SampleGeom &geo, const float *om, int *kw, float (*w)[NJ]) {
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        const double u = __dmul_rn(double(om[ax]), geo.C[ax]);
+        const double k0 = floor(u - 0.5 * geo.J) + 1.0;
+        const float f = float(u - k0 - (0.5 * geo.J - 1.0));
+        kw[ax] = wrap_first_tap(k0, geo.K[ax]);
+        poly_rows<NJ>(geo.coef[ax], geo.jp, geo.nq[ax], 2.0f * f - 1.0f, w[ax]);
+    }
+}
+
+// Unpacks a record already loaded as float4s.
+template <int NJ, int DIM>
+__device__ __forceinline__ void unpack_window(const float4 *r4, int *kw, float (*w)[NJ]) {
+    float r[4 * table_f4(DIM, NJ)];
+#pragma unroll
+    for (int q = 0; q < table_f4(DIM, NJ); ++q) {
+        r[4 * q] = r4[q].x;
+        r[4 * q + 1] = r4[q].y;
+        r[4 * q + 2] = r4[q].z;
+        r[4 * q + 3] = r4[q].w;
+    }
+    const unsigned k01 = __float_as_uint(r[0]), k2 = __float_as_uint(r[1]);
+    kw[0] = int(k01 & 0xffffu);
+    if (DIM > 1) kw[1 < DIM ? 1 : 0] = int(k01 >> 16);
+    if (DIM > 2) kw[2 < DIM ? 2 : 0] = int(k2 & 0xffffu);
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) w[ax][j] = r[2 + ax * NJ + j];
+    }
+}
+
+template <int NJ, int DIM>
+__device__ __forceinline__ void load_window_record(const SampleGeom &geo, int64_t i, float4 *r4) {
+    const float4 *src = reinterpret_cast<const float4 *>(geo.wtab + i * geo.wtab_stride);
+#pragma unroll
+    for (int q = 0; q < table_f4(DIM, NJ); ++q) r4[q] = src[q];
+}
+
+template <int NJ, int DIM>
+__global__ __launch_bounds__(256) void k_weight_table(SampleGeom geo, const float *om_sorted, int64_t M, float *out) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= M) return;
+    int kw[DIM];
+    float w[DIM][NJ];
+    eval_window<NJ, DIM>(geo, om_sorted + i * DIM, kw, w);
+    float r[4 * table_f4(DIM, NJ)];
+#pragma unroll
+    for (int q = 0; q < 4 * table_f4(DIM, NJ); ++q) r[q] = 0.f;
+    r[0] = __uint_as_float(unsigned(kw[0]) | (DIM > 1 ? unsigned(kw[1 < DIM ? 1 : 0]) << 16 : 0u));
+    r[1] = __uint_as_float(DIM > 2 ? unsigned(kw[2 < DIM ? 2 : 0]) : 0u);
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) r[2 + ax * NJ + j] = w[ax][j];
+    }
+    float4 *dst = reinterpret_cast<float4 *>(out + i * (4 * table_f4(DIM, NJ)));
+#pragma unroll
+    for (int q = 0; q < table_f4(DIM, NJ); ++q) dst[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+}
+
 // ------------------------------------------------------------ work distribution
 // Work items (gather chunks, gridding tile chunks) are ordered by decreasing
 // size on the host; workgroup b runs item b, and the hardware deals
@@ -876,13 +945,29 @@ __device__ __forceinline__ void interp_body(const InterpArgs &a, int64_t item) {
             const int64_t i = it.start + s;
             dst[k] = a.perm[i];
             int o = 0;
+            if (a.geo.wtab) {
+                // the window from the plan's table
+                constexpr int NJ = table_taps_c(J);
+                float4 r4[table_f4(DIM, NJ)];
+                load_window_record<NJ, DIM>(a.geo, i, r4);
+                int kw[DIM];
+                float wt[DIM][NJ];
+                unpack_window<NJ, DIM>(r4, kw, wt);
 #pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) {
-                int kk[J];
-                const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk);
-                window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[k][ax]);
-                if (a.geo.minmax) mm_sign_taps<J>(w[k][ax], mm_wrap_from(a.geo, ax, a.om_sorted[i * DIM + ax]));
-                o = o * E[ax] + (kk[0] - base[ax]);
+                for (int ax = 0; ax < DIM; ++ax) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) w[k][ax][j] = wt[ax][j];
+                    o = o * E[ax] + (kw[ax] - base[ax]);
+                }
+            } else {
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) {
+                    int kk[J];
+                    const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk);
+                    window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[k][ax]);
+                    if (a.geo.minmax) mm_sign_taps<J>(w[k][ax], mm_wrap_from(a.geo, ax, a.om_sorted[i * DIM + ax]));
+                    o = o * E[ax] + (kk[0] - base[ax]);
+                }
             }
             off[k] = o;
             if (a.geo.minmax) ph[k] = mm_phase<DIM>(a.geo, a.om_sorted + i * DIM);
@@ -1335,7 +1420,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_multi(const GridArgs *__r
 // item and their tiles are summed in LDS in wave order (deterministic).
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
-template <int DIM, int NJ, int MB, int GP>
+template <int DIM, int NJ, int MB, int GP, bool TAB>
 __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, int gg) {
     extern __shared__ float mf_lds[];
     __shared__ int seg_lo[kMaxNeighbors + 1];
@@ -1403,6 +1488,7 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
     // The global reads of a batch (trajectory, sample values) are issued one
     // batch ahead, so they are in flight while the wave walks the current one.
     float pom[DIM];
+    float4 prec[TAB ? table_f4(DIM, NJ) : 1];
     float2 pv[GP];
     bool pvalid = false;
     int cursor = 0;
@@ -1413,8 +1499,12 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
         if (pvalid) {
             const int f = f0 + s_idx;
             const int64_t i = seg_lo[sg] + (f - seg_pre[sg]);
+            if constexpr (TAB) {
+                load_window_record<NJ, DIM>(a.geo, i, prec);
+            } else {
 #pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) pom[ax] = a.om_sorted[i * DIM + ax];
+                for (int ax = 0; ax < DIM; ++ax) pom[ax] = a.om_sorted[i * DIM + ax];
+            }
             const int64_t src = a.y_sorted ? i : int64_t(a.perm[i]);
 #pragma unroll
             for (int q = 0; q < GP; ++q)
@@ -1427,13 +1517,22 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
         float *my = rec + lane * RS;
         {
             float2 ph = make_float2(1.f, 0.f);
-            if (pvalid && a.geo.minmax) ph = mm_phase<DIM>(a.geo, pom);
+            if constexpr (!TAB)
+                if (pvalid && a.geo.minmax) ph = mm_phase<DIM>(a.geo, pom);
 #pragma unroll
             for (int q = 0; q < GP; ++q) {
                 const float2 v = pvalid ? (a.geo.minmax ? cmulcj(ph, pv[q]) : pv[q]) : make_float2(0.f, 0.f);
                 my[2 * q] = v.x;
                 my[2 * q + 1] = v.y;
             }
+        }
+        int kwa[DIM];
+        float wva[DIM][NJ];
+        if (pvalid) {
+            if constexpr (TAB)
+                unpack_window<NJ, DIM>(prec, kwa, wva);
+            else
+                eval_window<NJ, DIM>(a.geo, pom, kwa, wva);
         }
 #pragma unroll
         for (int ax = 0; ax < DIM; ++ax) {
@@ -1442,14 +1541,10 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
 #pragma unroll 4
             for (int x = 0; x < T; ++x) E[x] = 0.f;
             if (pvalid) {
-                const double u = __dmul_rn(double(pom[ax]), a.geo.C[ax]);
-                const double k0 = floor(u - 0.5 * J) + 1.0;
-                const float fr = float(u - k0 - (0.5 * J - 1.0));
                 const int K = a.geo.K[ax];
-                const int kw = wrap_first_tap(k0, K);
+                const int kw = kwa[ax];
                 const int o = kw - base[ax];  // first tap relative to the tile, in [-base, K - base)
-                float wv[NJ];
-                poly_rows<NJ>(a.geo.coef[ax], a.geo.jp, a.geo.nq[ax], 2.0f * fr - 1.0f, wv);
+                float *wv = wva[ax];
                 if (a.geo.minmax) mm_sign_taps<NJ>(wv, K - kw);
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
@@ -1535,16 +1630,16 @@ __device__ __forceinline__ void grid_mfma_body(const GridArgs &a, int64_t item, 
     }
 }
 
-template <int DIM, int NJ, int MB, int GP>
+template <int DIM, int NJ, int MB, int GP, bool TAB>
 __global__ __launch_bounds__(256) void k_grid_mfma(GridArgs a) {
-    grid_mfma_body<DIM, NJ, MB, GP>(a, blockIdx.x, blockIdx.y);
+    grid_mfma_body<DIM, NJ, MB, GP, TAB>(a, blockIdx.x, blockIdx.y);
 }
 
-template <int DIM, int NJ, int MB, int GP>
+template <int DIM, int NJ, int MB, int GP, bool TAB>
 __global__ __launch_bounds__(256) void k_grid_mfma_multi(const GridArgs *__restrict__ jobs,
                                                         const int4 *__restrict__ blocks) {
     const int4 b = blocks[blockIdx.x];
-    grid_mfma_body<DIM, NJ, MB, GP>(jobs[b.x], b.y, b.z);
+    grid_mfma_body<DIM, NJ, MB, GP, TAB>(jobs[b.x], b.y, b.z);
 }
 
 // V^H on the matrix cores in 3D, by blocks.  The tile is T0 x T1 x 16 (T0,
@@ -1561,7 +1656,7 @@ __global__ __launch_bounds__(256) void k_grid_mfma_multi(const GridArgs *__restr
 // reaches.  Wavefronts synchronise only with themselves until the end, where
 // their tiles are summed in wave order (the result does not depend on
 // scheduling).
-template <int NJ, int T0, int T1>
+template <int NJ, int T0, int T1, bool TAB>
 __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, int g) {
     constexpr int T2 = 16;
     constexpr int NB1 = T1 / 4;
@@ -1609,8 +1704,10 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
         acc_re[q] = mfma_f4{0.f, 0.f, 0.f, 0.f};
         acc_im[q] = mfma_f4{0.f, 0.f, 0.f, 0.f};
     }
-    // trajectory and value of this lane's next sample, loaded one batch ahead
-    float pom[3];
+    // trajectory (or window record) and value of this lane's next sample,
+    // loaded one batch ahead
+    float pom[TAB ? 1 : 3];
+    float4 prec[TAB ? table_f4(3, NJ) : 1];
     float2 pv = make_float2(0.f, 0.f);
     bool pvalid = false;
     int cursor = 0;
@@ -1620,8 +1717,12 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
         const int sg = batch_segment(seg_pre, nseg, cursor, f0 + b + wave * 64, 64, f0 + s_idx);
         if (pvalid) {
             const int64_t i = seg_lo[sg] + (f0 + s_idx - seg_pre[sg]);
+            if constexpr (TAB) {
+                load_window_record<NJ, 3>(a.geo, i, prec);
+            } else {
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) pom[ax] = a.om_sorted[i * 3 + ax];
+                for (int ax = 0; ax < 3; ++ax) pom[ax] = a.om_sorted[i * 3 + ax];
+            }
             pv = a.y_sorted ? y[i] : y[a.perm[i]];
         }
     };
@@ -1636,20 +1737,31 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
         unsigned mk = 0;
         if (pvalid) {
             float *my = rec + lane * RS;
-            if (a.geo.minmax) pv = cmulcj(mm_phase<3>(a.geo, pom), pv);
+            if constexpr (!TAB)
+                if (a.geo.minmax) pv = cmulcj(mm_phase<3>(a.geo, pom), pv);
             my[0] = pv.x;
             my[1] = pv.y;
             unsigned bm[2] = {0u, 0u};
+            int kwa[3];
+            float wta[TAB ? 3 : 1][NJ];
+            if constexpr (TAB) unpack_window<NJ, 3>(prec, kwa, wta);
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                const double u = __dmul_rn(double(pom[ax]), a.geo.C[ax]);
-                const double k0 = floor(u - 0.5 * J) + 1.0;
-                const float fr = float(u - k0 - (0.5 * J - 1.0));
                 const int K = a.geo.K[ax];
-                const int kw = wrap_first_tap(k0, K);
                 float wv[NJ];
-                poly_rows<NJ>(a.geo.coef[ax], a.geo.jp, a.geo.nq[ax], 2.0f * fr - 1.0f, wv);
-                if (a.geo.minmax) mm_sign_taps<NJ>(wv, K - kw);
+                int kw;
+                if constexpr (TAB) {
+                    kw = kwa[ax];
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) wv[j] = wta[ax][j];
+                } else {
+                    const double u = __dmul_rn(double(pom[ax]), a.geo.C[ax]);
+                    const double k0 = floor(u - 0.5 * J) + 1.0;
+                    const float fr = float(u - k0 - (0.5 * J - 1.0));
+                    kw = wrap_first_tap(k0, K);
+                    poly_rows<NJ>(a.geo.coef[ax], a.geo.jp, a.geo.nq[ax], 2.0f * fr - 1.0f, wv);
+                    if (a.geo.minmax) mm_sign_taps<NJ>(wv, K - kw);
+                }
                 if (a.nt[ax] > 1) {
                     // first tap relative to the tile, in [-(J-1), T): a window
                     // wrapping in from the top of the axis comes in negative
@@ -1748,16 +1860,16 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
     }
 }
 
-template <int NJ, int T0, int T1>
+template <int NJ, int T0, int T1, bool TAB>
 __global__ __launch_bounds__(256) void k_grid_blk(GridArgs a) {
-    grid_blk_body<NJ, T0, T1>(a, blockIdx.x, blockIdx.y);
+    grid_blk_body<NJ, T0, T1, TAB>(a, blockIdx.x, blockIdx.y);
 }
 
-template <int NJ, int T0, int T1>
+template <int NJ, int T0, int T1, bool TAB>
 __global__ __launch_bounds__(256) void k_grid_blk_multi(const GridArgs *__restrict__ jobs,
                                                        const int4 *__restrict__ blocks) {
     const int4 b = blocks[blockIdx.x];
-    grid_blk_body<NJ, T0, T1>(jobs[b.x], b.y, b.z);
+    grid_blk_body<NJ, T0, T1, TAB>(jobs[b.x], b.y, b.z);
 }
 
 // Sums the partial tiles of every split tile in chunk order; one workgroup per
@@ -2365,23 +2477,35 @@ hipError_t launch_grid_d(const GridArgs &a, hipStream_t s) {
     }
 }
 
-template <int DIM, int NJ, int MB>
-hipError_t launch_grid_mfma_m(const GridArgs &a, hipStream_t s) {
+// The window-table form of the sample kernels exists for windows of up to 8
+// taps (table_taps 6 or 8); wider windows evaluate the kernel on the fly even
+// when the plan holds a table.
+inline bool use_table(const SampleGeom &g) { return g.wtab != nullptr && table_taps(g.J) <= 8; }
+
+template <int DIM, int NJ, int MB, bool TAB>
+hipError_t launch_grid_mfma_t(const GridArgs &a, hipStream_t s) {
     const size_t lds = grid_lds(a);
     const int gp = a.grids_per_wg;
     const dim3 grid(unsigned(a.n_items), unsigned((a.grids + gp - 1) / gp));
     switch (gp) {
-        case 1: launch_kernel((k_grid_mfma<DIM, NJ, MB, 1>), grid, dim3(256), lds, s, a); break;
-        case 2: launch_kernel((k_grid_mfma<DIM, NJ, MB, 2>), grid, dim3(256), lds, s, a); break;
+        case 1: launch_kernel((k_grid_mfma<DIM, NJ, MB, 1, TAB>), grid, dim3(256), lds, s, a); break;
+        case 2: launch_kernel((k_grid_mfma<DIM, NJ, MB, 2, TAB>), grid, dim3(256), lds, s, a); break;
         case 4:
             if constexpr (MB <= 2) {
-                launch_kernel((k_grid_mfma<DIM, NJ, MB, 4>), grid, dim3(256), lds, s, a);
+                launch_kernel((k_grid_mfma<DIM, NJ, MB, 4, TAB>), grid, dim3(256), lds, s, a);
                 break;
             }
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int DIM, int NJ, int MB>
+hipError_t launch_grid_mfma_m(const GridArgs &a, hipStream_t s) {
+    if constexpr (NJ <= 8)
+        if (use_table(a.geo)) return launch_grid_mfma_t<DIM, NJ, MB, true>(a, s);
+    return launch_grid_mfma_t<DIM, NJ, MB, false>(a, s);
 }
 
 template <int DIM, int NJ>
@@ -2406,16 +2530,23 @@ hipError_t launch_grid_mfma_d(const GridArgs &a, hipStream_t s) {
 template <int NJ, bool MULTI>
 hipError_t launch_grid_blk_j(const GridArgs &a, const GridArgs *jobs, const int4 *blocks, int64_t nblocks,
                              size_t lds, hipStream_t s) {
-#define NUFFT_BLK_CASE(T0, T1)                                                                               \
-    if (a.T[0] == T0 && a.T[1] == T1) {                                                                      \
-        if (MULTI)                                                                                           \
-            launch_kernel((k_grid_blk_multi<NJ, T0, T1>), dim3(unsigned(nblocks)), dim3(256), lds, s, jobs,  \
-                          blocks);                                                                           \
-        else                                                                                                 \
-            launch_kernel((k_grid_blk<NJ, T0, T1>), dim3(unsigned(a.n_items), unsigned(a.grids)), dim3(256), \
-                          lds, s, a);                                                                        \
-        return hipGetLastError();                                                                            \
+#define NUFFT_BLK_CASE(T0, T1)                                                                                 \
+    if (a.T[0] == T0 && a.T[1] == T1) {                                                                        \
+        if (MULTI && tab)                                                                                      \
+            launch_kernel((k_grid_blk_multi<NJ, T0, T1, true>), dim3(unsigned(nblocks)), dim3(256), lds, s,    \
+                          jobs, blocks);                                                                       \
+        else if (MULTI)                                                                                        \
+            launch_kernel((k_grid_blk_multi<NJ, T0, T1, false>), dim3(unsigned(nblocks)), dim3(256), lds, s,   \
+                          jobs, blocks);                                                                       \
+        else if (tab)                                                                                          \
+            launch_kernel((k_grid_blk<NJ, T0, T1, true>), dim3(unsigned(a.n_items), unsigned(a.grids)),        \
+                          dim3(256), lds, s, a);                                                               \
+        else                                                                                                   \
+            launch_kernel((k_grid_blk<NJ, T0, T1, false>), dim3(unsigned(a.n_items), unsigned(a.grids)),       \
+                          dim3(256), lds, s, a);                                                               \
+        return hipGetLastError();                                                                              \
     }
+    const bool tab = NJ <= 8 && use_table(a.geo);
     NUFFT_BLK_CASE(8, 8)
     NUFFT_BLK_CASE(8, 16)
     NUFFT_BLK_CASE(16, 8)
@@ -2489,14 +2620,15 @@ size_t grid_lds(const GridArgs &a) {
 }
 
 namespace {
-template <int DIM, int NJ, int MB>
-hipError_t grid_mfma_multi_m(const GridArgs *jobs, const int4 *blocks, int64_t n, int gp, size_t lds, hipStream_t s) {
+template <int DIM, int NJ, int MB, bool TAB>
+hipError_t grid_mfma_multi_t(const GridArgs *jobs, const int4 *blocks, int64_t n, int gp, size_t lds, hipStream_t s) {
+    const dim3 grid = dim3(unsigned(n));
     switch (gp) {
-        case 1: launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 1>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
-        case 2: launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 2>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks); break;
+        case 1: launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 1, TAB>), grid, dim3(256), lds, s, jobs, blocks); break;
+        case 2: launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 2, TAB>), grid, dim3(256), lds, s, jobs, blocks); break;
         case 4:
             if constexpr (MB <= 2) {
-                launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 4>), dim3(unsigned(n)), dim3(256), lds, s, jobs, blocks);
+                launch_kernel((k_grid_mfma_multi<DIM, NJ, MB, 4, TAB>), grid, dim3(256), lds, s, jobs, blocks);
                 break;
             }
             return hipErrorInvalidValue;
@@ -2505,13 +2637,21 @@ hipError_t grid_mfma_multi_m(const GridArgs *jobs, const int4 *blocks, int64_t n
     return hipGetLastError();
 }
 
-template <int DIM, int NJ>
-hipError_t grid_mfma_multi_j(const GridArgs *jobs, const int4 *blocks, int64_t n, int mb, int gp, size_t lds,
+template <int DIM, int NJ, int MB>
+hipError_t grid_mfma_multi_m(const GridArgs *jobs, const int4 *blocks, int64_t n, int gp, bool tab, size_t lds,
                              hipStream_t s) {
+    if constexpr (NJ <= 8)
+        if (tab) return grid_mfma_multi_t<DIM, NJ, MB, true>(jobs, blocks, n, gp, lds, s);
+    return grid_mfma_multi_t<DIM, NJ, MB, false>(jobs, blocks, n, gp, lds, s);
+}
+
+template <int DIM, int NJ>
+hipError_t grid_mfma_multi_j(const GridArgs *jobs, const int4 *blocks, int64_t n, int mb, int gp, bool tab,
+                             size_t lds, hipStream_t s) {
     switch (mb) {
-        case 1: return grid_mfma_multi_m<DIM, NJ, 1>(jobs, blocks, n, gp, lds, s);
-        case 2: return grid_mfma_multi_m<DIM, NJ, 2>(jobs, blocks, n, gp, lds, s);
-        case 4: return grid_mfma_multi_m<DIM, NJ, 4>(jobs, blocks, n, gp, lds, s);
+        case 1: return grid_mfma_multi_m<DIM, NJ, 1>(jobs, blocks, n, gp, tab, lds, s);
+        case 2: return grid_mfma_multi_m<DIM, NJ, 2>(jobs, blocks, n, gp, tab, lds, s);
+        case 4: return grid_mfma_multi_m<DIM, NJ, 4>(jobs, blocks, n, gp, tab, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2520,9 +2660,10 @@ template <int DIM>
 hipError_t grid_mfma_multi_d(const GridArgs *jobs, const int4 *blocks, int64_t n, const GridArgs &p, size_t lds,
                              hipStream_t s) {
     const int mb = p.tile_cells / 256;
-    if (p.geo.J <= 6) return grid_mfma_multi_j<DIM, 6>(jobs, blocks, n, mb, p.grids_per_wg, lds, s);
-    if (p.geo.J <= 8) return grid_mfma_multi_j<DIM, 8>(jobs, blocks, n, mb, p.grids_per_wg, lds, s);
-    return grid_mfma_multi_j<DIM, 16>(jobs, blocks, n, mb, p.grids_per_wg, lds, s);
+    const bool tab = use_table(p.geo);
+    if (p.geo.J <= 6) return grid_mfma_multi_j<DIM, 6>(jobs, blocks, n, mb, p.grids_per_wg, tab, lds, s);
+    if (p.geo.J <= 8) return grid_mfma_multi_j<DIM, 8>(jobs, blocks, n, mb, p.grids_per_wg, tab, lds, s);
+    return grid_mfma_multi_j<DIM, 16>(jobs, blocks, n, mb, p.grids_per_wg, tab, lds, s);
 }
 
 template <int DIM, int LS>
@@ -2602,6 +2743,28 @@ hipError_t launch_dc_update(float *w, const float2 *u, float2 *wc, int64_t M, fl
     if (M == 0) return hipSuccess;
     launch_kernel(k_dc_update, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, w, u, wc, M, inv_c);
     return hipGetLastError();
+}
+
+template <int NJ>
+hipError_t launch_weight_table_j(const SampleGeom &g, const float *om_sorted, int64_t M, float *out, hipStream_t s) {
+    const dim3 grid(unsigned((M + 255) / 256));
+    switch (g.d) {
+        case 1: launch_kernel((k_weight_table<NJ, 1>), grid, dim3(256), 0, s, g, om_sorted, M, out); break;
+        case 2: launch_kernel((k_weight_table<NJ, 2>), grid, dim3(256), 0, s, g, om_sorted, M, out); break;
+        case 3: launch_kernel((k_weight_table<NJ, 3>), grid, dim3(256), 0, s, g, om_sorted, M, out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_weight_table(const SampleGeom &g, const float *om_sorted, int64_t M, float *out, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    if (g.wtab_stride != table_stride(g.d, g.J)) return hipErrorInvalidValue;
+    switch (table_taps(g.J)) {
+        case 6: return launch_weight_table_j<6>(g, om_sorted, M, out, s);
+        case 8: return launch_weight_table_j<8>(g, om_sorted, M, out, s);
+        default: return launch_weight_table_j<16>(g, om_sorted, M, out, s);
+    }
 }
 
 hipError_t launch_real_to_complex(const float *w, float2 *wc, int64_t M, float scale, hipStream_t s) {

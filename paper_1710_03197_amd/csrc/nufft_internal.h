@@ -161,7 +161,17 @@ struct SampleGeom {
     const float *dcoef[kMaxDim];  // [nq_d][jp]
     int minmax;           // min-max interpolator: real factors c' in coef, plus
                           // the per-sample phase e^{i sum omega/2} and tap signs
+    // Optional table of every sorted sample's window, made with the plan
+    // (nullptr: the sample kernels evaluate it on the fly).  Record of
+    // wtab_stride floats per sample: the wrapped first taps as 16-bit fields
+    // (k0 | k1 << 16, then k2), then table_taps(J) weights per axis (zero
+    // past J), zero padded to a multiple of 4 floats.
+    const float *wtab;
+    int wtab_stride;
 };
+inline int table_taps(int J) { return J <= 6 ? 6 : J <= 8 ? 8 : 16; }
+inline int table_stride(int d, int J) { return (2 + d * table_taps(J) + 3) & ~3; }
+hipError_t launch_weight_table(const SampleGeom &g, const float *om_sorted, int64_t M, float *out, hipStream_t s);
 
 // Interpolation V: y[g][perm[i]] = sum_taps w * G[g][..] for sorted sample i.
 // With items, one workgroup per (bin, chunk) stages the tile plus halo in LDS;

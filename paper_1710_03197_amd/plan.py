@@ -49,6 +49,7 @@ def options_struct(options: dict | None) -> "_lib.PlanOptions":
     opt.fuse_reduce = int(options.get("fuse_reduce", 0))
     opt.grid_mfma = int(options.get("grid_mfma", 0))
     opt.interp_merge = int(options.get("interp_merge", 0))
+    opt.weight_table = int(options.get("weight_table", 0))
     interp = options.get("interpolator", 0)
     opt.interpolator = {"kb": 0, "kaiser-bessel": 0, "minmax": 1, "min-max": 1}.get(interp, interp) \
         if isinstance(interp, str) else int(interp)

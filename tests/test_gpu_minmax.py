@@ -98,3 +98,7 @@ def test_minmax_rejects_gradients_and_density(dev):
             p.density_compensation(2)
     with pytest.raises(NufftError):
         Plan(_t(om, dev), (16, 16), (32, 32), 6, options=dict(interpolator=2))
+    # the window table holds Kaiser-Bessel weights only
+    with pytest.raises(NufftError) as ei:
+        Plan(_t(om, dev), (16, 16), (32, 32), 6, options=dict(interpolator=1, weight_table=1))
+    assert ei.value.code == "NUFFT_ERR_UNSUPPORTED"

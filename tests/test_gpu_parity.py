@@ -175,9 +175,10 @@ def test_nonfinite_trajectory_rejected(dev):
 
 
 @pytest.mark.parametrize("opts", [dict(interp_merge=-1), dict(fuse_reduce=3), dict(presort=3), dict(grid_chunk=32),
-                                  dict(fft_groups=-1), dict(grid_mfma=4), dict(interpolator=2)],
+                                  dict(fft_groups=-1), dict(grid_mfma=4), dict(interpolator=2),
+                                  dict(weight_table=2)],
                          ids=["interp_merge", "fuse_reduce", "presort", "grid_chunk", "fft_groups", "grid_mfma",
-                              "interpolator"])
+                              "interpolator", "weight_table"])
 def test_out_of_range_options_rejected(dev, opts):
     """Every tuning knob outside its documented range is an argument error."""
     from paper_1710_03197_amd import NufftError, Plan
@@ -323,6 +324,12 @@ OPTION_CASES = [
     ((32, 32, 32), dict(tile=(8, 16, 16), fuse_reduce=1)),
     ((4, 4, 8), dict(tile=(8, 8, 16))),                            # every axis one tile: wrapped windows
     ((64, 64), dict(tile=(16, 16), interp_merge=4)),             # gather items over runs of tiles
+    ((64, 64), dict(tile=(16, 16), weight_table=1)),             # windows from the plan's table
+    ((64, 64), dict(tile=(32, 16), weight_table=1, interp_merge=2, presort=1)),
+    ((16, 16, 16), dict(tile=(8, 8, 16), weight_table=1)),
+    ((16, 16, 16), dict(tile=(8, 8, 16), grid_mfma=3, weight_table=1)),
+    ((4, 4, 8), dict(tile=(8, 8, 16), weight_table=1)),
+    ((64,), dict(tile=(16,), weight_table=1)),
     ((16, 16, 16), dict(tile=(8, 8, 8), interp_merge=3)),
     ((64,), dict(tile=(16,), interp_merge=5)),
 ]

@@ -52,6 +52,10 @@ def _case(seed):
         v = int(r.choice(vals))
         if v:
             opts[key] = v
+    # the window table, drawn from a stream of its own (the draws above keep
+    # their configurations)
+    if np.random.default_rng(1000 + seed).random() < 0.5:
+        opts["weight_table"] = 1
     return N, K, J, om.astype(np.float32), opts
 
 
