@@ -251,7 +251,10 @@ def bench_2d(dev, steps, warmup, orc_mod, tune="cache", no_graph=False):
     plan.close()
     # the paper's default interpolator (min-max) on the same workload: parity
     # on 2048 sampled outputs against the oracle's direct definition, then time
-    pm = Plan(torch.from_numpy(om).to(dev), N, K, J, options=dict(opts, interpolator="minmax"))
+    # (the window table holds Kaiser-Bessel weights only: min-max plans
+    # evaluate their coefficients on the fly)
+    mm_opts = {k: v for k, v in opts.items() if k != "weight_table"}
+    pm = Plan(torch.from_numpy(om).to(dev), N, K, J, options=dict(mm_opts, interpolator="minmax"))
     pm.forward(x, out=y)
     torch.cuda.synchronize()
     pick = np.random.default_rng(0).choice(M, 2048, replace=False)
@@ -307,7 +310,9 @@ def bench_batched(dev, steps, warmup, orc_mod, n_problems=24):
     oms = [torch.from_numpy(p["om"]).to(dev) for p in probs]
     coils = [torch.from_numpy(p["coils"]).to(dev) for p in probs]
     xs = [torch.from_numpy(p["x"]).to(dev) for p in probs]
-    mp = MultiPlan([dict(om=o, N=p["N"], coils=c) for o, p, c in zip(oms, probs, coils)], J=6)
+    # both sides take each problem's options from the shipped tuning cache
+    # (tuned in coil mode for these sizes), defaults where it has none
+    mp = MultiPlan([dict(om=o, N=p["N"], coils=c) for o, p, c in zip(oms, probs, coils)], J=6, tune="cache")
     ys = mp.forward(xs)
     xa = mp.adjoint(ys)
     torch.cuda.synchronize()
@@ -319,7 +324,10 @@ def bench_batched(dev, steps, warmup, orc_mod, n_problems=24):
     print(f"[bench] batched parity: {[f'{e:.2e}' for e in errs]}", flush=True)
     if max(errs) > TOL:
         raise SystemExit("batched parity gate failed")
-    singles = [Plan(o, p["N"], p["K"], 6) for o, p in zip(oms, probs)]
+    from paper_1710_03197_amd import autotune
+    singles = [Plan(o, p["N"], p["K"], 6, options=autotune.cached_options(p["N"], p["K"], 6, int(o.shape[0]),
+                                                                           autotune.SHIPPED_CACHE, dev, C))
+               for o, p in zip(oms, probs)]
     cxs = [c * x[None] for c, x in zip(coils, xs)]
     ybuf = [torch.empty((C, p["om"].shape[0]), dtype=torch.complex64, device=dev) for p in probs]
     xbuf = [torch.empty_like(cx) for cx in cxs]

@@ -120,6 +120,11 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *                 interpolator, Section 2.1 "Interpolation"); Kaiser-Bessel
  *                 only (with min-max: NUFFT_ERR_UNSUPPORTED); 0: evaluate on
  *                 the fly
+ *   fft_radix     radix schedule of the Stockham FFT passes on every axis
+ *                 (Section 2.1 "Oversampled FFT"): 0: radices 8, 4, 2, 3, 5
+ *                 taken greedily in that order; 1: 4, 8, 2, 3, 5; 2: 3, 5,
+ *                 8, 4, 2; 3: schedule 0's passes in reverse order
+ *   reserved      must be 0
  *   interp_merge  most grid tiles along the last axis that one interpolation
  *                 work item covers when their samples are few (>= 1; the
  *                 region it stages must fit 64 KiB of LDS, wider runs are
@@ -137,6 +142,8 @@ typedef struct {
     int interpolator;
     int interp_merge;
     int weight_table;
+    int fft_radix;
+    int reserved[3];
 } nufft_options_t;
 
 /* nufft_plan with tuning options (opt may be NULL = defaults). */

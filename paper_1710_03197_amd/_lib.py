@@ -41,7 +41,8 @@ class PlanOptions(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int * 3), ("grid_chunk", ctypes.c_int), ("fft_groups", ctypes.c_int),
                 ("interp_direct", ctypes.c_int), ("presort", ctypes.c_int),
                 ("fuse_reduce", ctypes.c_int), ("grid_mfma", ctypes.c_int), ("interpolator", ctypes.c_int),
-                ("interp_merge", ctypes.c_int), ("weight_table", ctypes.c_int)]
+                ("interp_merge", ctypes.c_int), ("weight_table", ctypes.c_int), ("fft_radix", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class ProblemDesc(ctypes.Structure):

@@ -3,9 +3,12 @@
 Chooses, per workload, the grid tile shape used for binning, gathering and
 gridding, the number of samples per gridding work item, whether the gather
 stages tiles in LDS or reads the grid directly, whether the gridding reads the
-samples pre-permuted into sorted order, how many workgroups the FFT passes aim
-for (lines or columns per workgroup), and whether the first inverse FFT pass
-sums the partial tiles of split gridding tiles.  These
+samples pre-permuted into sorted order, whether the sample kernels read a
+precomputed window table or evaluate the kernel per sample, how many
+workgroups the FFT passes aim for (lines or columns per workgroup), the FFT's
+radix schedule, and whether the first inverse FFT pass sums the partial tiles
+of split gridding tiles.  A workload with coil maps is tuned in coil mode.
+These
 change only speed: every candidate's forward and adjoint outputs must agree
 with the default plan's to 1e-5 (relative L2) before it may win, and the
 default plan is the one the parity tests hold to the FP64 oracle.
@@ -23,17 +26,18 @@ import time
 
 import torch
 
-from .plan import Plan
+from .plan import Plan as _Plan
 
 TOL = 1e-5
 
 TILE_CANDIDATES = {
     1: [(32,), (64,), (16,)],
     2: [(32, 16), (64, 16), (16, 16), (32, 32), (16, 32), (64, 8)],
-    3: [(8, 8, 16), (8, 8, 8), (4, 8, 16), (8, 4, 16), (4, 4, 16), (16, 8, 8)],
+    3: [(8, 8, 16), (16, 8, 16), (8, 16, 16), (8, 8, 8), (4, 8, 16), (4, 4, 16), (16, 8, 8)],
 }
 CHUNK_CANDIDATES = [256, 512, 1024, 2048]
 FFT_GROUP_CANDIDATES = [256, 512, 1024, 2048, 4096]
+RADIX_CANDIDATES = [1, 2, 3]  # fft_radix schedules besides the default 0
 
 
 def cache_path(path: str | None = None) -> str:
@@ -45,10 +49,11 @@ def cache_path(path: str | None = None) -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "nufft_mi355x", "tune.json")
 
 
-def workload_key(N, K, J, M, device=None) -> str:
+def workload_key(N, K, J, M, device=None, C: int = 0) -> str:
     arch = torch.cuda.get_device_properties(device or 0).gcnArchName.split(":")[0]
     mb = 1 << max(0, int(round(math.log2(max(M, 1)))))
-    return f"{arch}|d{len(N)}|N{'x'.join(map(str, N))}|K{'x'.join(map(str, K))}|J{J}|M~{mb}"
+    key = f"{arch}|d{len(N)}|N{'x'.join(map(str, N))}|K{'x'.join(map(str, K))}|J{J}|M~{mb}"
+    return key + (f"|C{C}" if C else "")
 
 
 def _load(path):
@@ -76,26 +81,34 @@ def _time(fn, reps):
 
 
 def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | None = None,
-         save: bool = True, verbose: bool = False) -> dict:
-    """Tune the plan options for trajectory `om` (float32 [M, d] on the GPU).
+         save: bool = True, verbose: bool = False, coils: torch.Tensor | None = None) -> dict:
+    """Tune the plan options for trajectory `om` (float32 [M, d] on the GPU),
+    in coil mode when `coils` (complex64 [C, *N]) is given.
     Returns {"options": ..., "ms_pair": ..., "default_ms_pair": ..., "tried": n}."""
     N = tuple(int(n) for n in N)
     K = tuple(2 * n for n in N) if K is None else tuple(int(k) for k in K)
     d, M = len(N), int(om.shape[0])
+    C = 0 if coils is None else int(coils.shape[0])
     dev = om.device
     g = torch.Generator(device="cpu").manual_seed(1234)
     x = torch.complex(torch.randn(N, generator=g), torch.randn(N, generator=g)).to(dev)
-    yin = torch.complex(torch.randn(M, generator=g), torch.randn(M, generator=g)).to(dev)
+    ys = (max(C, 1), M) if C else (M,)
+    yin = torch.complex(torch.randn(ys, generator=g), torch.randn(ys, generator=g)).to(dev)
+
+    def Plan(om_, N_, K_, J_, options=None):  # noqa: N802 - every candidate in the workload's coil mode
+        return _Plan(om_, N_, K_, J_, coils=coils, options=options)
 
     ref = Plan(om, N, K, J)
     y_ref, x_ref = ref.forward(x), ref.adjoint(yin)
 
     def pair_time(p):
-        y = torch.empty(M, dtype=torch.complex64, device=dev)
+        y = torch.empty(ys, dtype=torch.complex64, device=dev)
         xa = torch.empty(N, dtype=torch.complex64, device=dev)
         return _time(lambda: (p.forward(x, out=y), p.adjoint(yin, out=xa)), reps)
 
     def sample_stage_time(p):
+        if C:  # coil mode: the stage calls take single grids, so time the pair
+            return pair_time(p)
         G = torch.empty(K, dtype=torch.complex64, device=dev)
         return _time(lambda: (p.stage_v(G), p.stage_vh(yin)), reps)
 
@@ -128,7 +141,7 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
     #    the gridding's samples pre-permuted into sorted order or read through
     #    the permutation, and runs of sparse tiles per gather item
     for extra in (dict(interp_direct=1), dict(presort=1), dict(presort=2), dict(interp_merge=1),
-                  dict(interp_merge=2), dict(interp_merge=4)):
+                  dict(interp_merge=2), dict(interp_merge=4), dict(weight_table=1)):
         opts = dict(best, **extra)
         p = Plan(om, N, K, J, options=opts)
         tried += 1
@@ -154,7 +167,22 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
             print(f"[tune] {opts}: pair {t:.4f} ms", flush=True)
         if t < best_pt:
             best_pair, best_pt = opts, t
-    # 4) split tiles' partial sums in the first inverse FFT pass or apart
+    # 4) the FFT radix schedule, timed on the whole pair
+    for radix in RADIX_CANDIDATES:
+        opts = dict(best_pair, fft_radix=radix)
+        try:
+            p = Plan(om, N, K, J, options=opts)
+        except RuntimeError:
+            continue
+        tried += 1
+        if valid(p):
+            t = pair_time(p)
+            if verbose:
+                print(f"[tune] {opts}: pair {t:.4f} ms", flush=True)
+            if t < best_pt:
+                best_pair, best_pt = opts, t
+        p.close()
+    # 5) split tiles' partial sums in the first inverse FFT pass or apart
     if d >= 2:
         for fuse in (1, 2):
             opts = dict(best_pair, fuse_reduce=fuse)
@@ -173,7 +201,7 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
         cp = cache_path(path)
         os.makedirs(os.path.dirname(cp), exist_ok=True)
         db = _load(cp)
-        db[workload_key(N, K, J, M, dev)] = result
+        db[workload_key(N, K, J, M, dev, C)] = result
         tmp = cp + ".tmp"
         with open(tmp, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)
@@ -181,10 +209,15 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
     return result
 
 
-def cached_options(N, K, J, M, path: str | None = None, device=None) -> dict | None:
+def cached_options(N, K, J, M, path: str | None = None, device=None, C: int = 0) -> dict | None:
+    """The cached options of a workload (C: coils; a coil-mode entry falls
+    back to the single-coil one)."""
     N = tuple(int(n) for n in N)
     K = tuple(2 * n for n in N) if K is None else tuple(int(k) for k in K)
-    entry = _load(cache_path(path)).get(workload_key(N, K, J, M, device))
+    db = _load(cache_path(path))
+    entry = db.get(workload_key(N, K, J, M, device, C)) if C else None
+    if entry is None:
+        entry = db.get(workload_key(N, K, J, M, device))
     return None if entry is None else entry["options"]
 
 
@@ -192,10 +225,11 @@ def tuned_plan(om: torch.Tensor, N, K=None, J: int = 6, coils=None, path: str | 
                tune_if_missing: bool = False) -> Plan:
     """A Plan with the cached tuned options for this workload (tuning first if
     asked and nothing is cached; defaults otherwise)."""
-    opts = cached_options(N, K, J, int(om.shape[0]), path, om.device)
+    C = 0 if coils is None else int(coils.shape[0])
+    opts = cached_options(N, K, J, int(om.shape[0]), path, om.device, C)
     if opts is None and tune_if_missing:
-        opts = tune(om, N, K, J, path=path)["options"]
-    return Plan(om, N, K, J, coils=coils, options=opts)
+        opts = tune(om, N, K, J, path=path, coils=coils)["options"]
+    return _Plan(om, N, K, J, coils=coils, options=opts)
 
 
 SHIPPED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
@@ -203,17 +237,32 @@ SHIPPED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 
 def _main():
     """Tune the benchmark workloads and write the cache:
-    python -m paper_1710_03197_amd.autotune --out FILE [--configs 2 3]"""
+    python -m paper_1710_03197_amd.autotune --out FILE [--configs 1 2 3 4]
+    (4: one problem per distinct image size and sample-count bucket of the
+    uneven spiral batch, in coil mode)"""
     import argparse
     from . import data
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--configs", nargs="*", type=int, default=[1, 2, 3])
+    ap.add_argument("--configs", nargs="*", type=int, default=[1, 2, 3, 4])
     ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     makers = {1: data.config1, 2: data.config2, 3: data.config3}
     dev = torch.device("cuda:0")
     for k in args.configs:
+        if k == 4:
+            seen = set()
+            for pr in data.config4():
+                om = torch.from_numpy(pr["om"]).to(dev)
+                key = workload_key(pr["N"], pr["K"], 6, om.shape[0], dev, pr["coils"].shape[0])
+                if key in seen:
+                    continue
+                seen.add(key)
+                coils = torch.from_numpy(pr["coils"]).to(dev)
+                res = tune(om, pr["N"], pr["K"], 6, reps=max(3, args.reps // 4), path=args.out, verbose=False,
+                           coils=coils)
+                print(f"config 4 {key}: {res}", flush=True)
+            continue
         c = makers[k]()
         om = torch.from_numpy(c["om"]).to(dev)
         res = tune(om, c["N"], c["K"], c["J"], reps=args.reps, path=args.out, verbose=True)

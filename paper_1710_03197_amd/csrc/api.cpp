@@ -1498,6 +1498,10 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     if (opt && (opt->interpolator < 0 || opt->interpolator > 1))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "interpolator takes 0 (Kaiser-Bessel) or 1 (min-max)"));
     p->minmax = opt && opt->interpolator == 1;
+    if (opt && (opt->reserved[0] || opt->reserved[1] || opt->reserved[2]))
+        return bail(fail(NUFFT_ERR_INVALID_ARG, "reserved option fields must be 0"));
+    if (opt && (opt->fft_radix < 0 || opt->fft_radix > 3))
+        return bail(fail(NUFFT_ERR_INVALID_ARG, "fft_radix takes 0, 1, 2 or 3"));
     if (opt && (opt->weight_table < 0 || opt->weight_table > 1))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "weight_table takes 0 or 1"));
     p->use_wtab = opt && opt->weight_table == 1;
@@ -1507,7 +1511,8 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         const double beta = kb_beta(J, double(K[a]) / double(N[a]));
         if (p->minmax ? !minmax_fit(int(N[a]), int(K[a]), J, beta, &p->ker[a]) : !kb_fit(J, beta, &p->ker[a]))
             return bail(fail(NUFFT_ERR_UNSUPPORTED, "kernel polynomial fit did not converge"));
-        if (!radix_plan(int(K[a]), &p->rp[a])) return bail(fail(NUFFT_ERR_UNSUPPORTED, "no radix plan for K"));
+        if (!radix_plan(int(K[a]), &p->rp[a], opt ? opt->fft_radix : 0))
+            return bail(fail(NUFFT_ERR_UNSUPPORTED, "no radix plan for K"));
         const int target = (opt && opt->tile[a] > 0) ? opt->tile[a] : targets[d - 1][a];
         p->T[a] = choose_tile(K[a], target, std::max(1, need));
         p->nt[a] = int(K[a] / p->T[a]);

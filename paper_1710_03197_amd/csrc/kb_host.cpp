@@ -4,6 +4,7 @@
 // the scaling stage S (Section 2.1 "Scaling"), the per-tap polynomial fit the
 // GPU evaluates, FFT twiddles and the radix schedule of the oversampled FFT
 // (Section 2.1 "Oversampled FFT").
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -305,11 +306,14 @@ std::vector<float2> twiddles(int K) {
     return tw;
 }
 
-bool radix_plan(int K, RadixPlan *rp) {
+bool radix_plan(int K, RadixPlan *rp, int schedule) {
     rp->n = 0;
     int rem = K;
-    const int order[] = {8, 4, 2, 3, 5};
-    for (int r : order) {
+    // radices taken greedily in this order (schedule 3: schedule 0's passes
+    // run in reverse)
+    static const int orders[3][5] = {{8, 4, 2, 3, 5}, {4, 8, 2, 3, 5}, {3, 5, 8, 4, 2}};
+    if (schedule < 0 || schedule > 3) return false;
+    for (int r : orders[schedule == 3 ? 0 : schedule]) {
         while (rem % r == 0) {
             if (rp->n >= kMaxPasses) return false;
             rp->r[rp->n++] = r;
@@ -317,6 +321,7 @@ bool radix_plan(int K, RadixPlan *rp) {
         }
     }
     if (rem != 1) return false;
+    if (schedule == 3) std::reverse(rp->r, rp->r + rp->n);
     auto magic = [](int D) { return D > 1 ? 0xFFFFFFFFu / unsigned(D) + 1u : 0u; };
     int Ns = 1;
     for (int p = 0; p < rp->n; ++p) {

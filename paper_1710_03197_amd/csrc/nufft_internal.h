@@ -75,8 +75,10 @@ std::vector<float2> half_phase(int K);
 std::vector<float> kb_scaling(int N, int K, int J, double beta);
 // Twiddles e^{-2 pi i e / K}, e in [0, K), computed in float64.
 std::vector<float2> twiddles(int K);
-// Stockham radix schedule; false if K has a prime factor above 5.
-bool radix_plan(int K, RadixPlan *rp);
+// Stockham radix schedule; false if K has a prime factor above 5.  schedule
+// 0: radices 8, 4, 2, 3, 5 taken greedily in that order (the default); 1: 4,
+// 8, 2, 3, 5; 2: 3, 5, 8, 4, 2; 3: schedule 0 with its passes reversed.
+bool radix_plan(int K, RadixPlan *rp, int schedule = 0);
 
 // ---- device kernel launchers (kernels.hip).  All asynchronous on `s`.
 

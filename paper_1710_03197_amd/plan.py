@@ -50,6 +50,7 @@ def options_struct(options: dict | None) -> "_lib.PlanOptions":
     opt.grid_mfma = int(options.get("grid_mfma", 0))
     opt.interp_merge = int(options.get("interp_merge", 0))
     opt.weight_table = int(options.get("weight_table", 0))
+    opt.fft_radix = int(options.get("fft_radix", 0))
     interp = options.get("interpolator", 0)
     opt.interpolator = {"kb": 0, "kaiser-bessel": 0, "minmax": 1, "min-max": 1}.get(interp, interp) \
         if isinstance(interp, str) else int(interp)
@@ -382,7 +383,8 @@ class MultiPlan:
             options = pr.get("options")
             if options is None and tune == "cache":
                 from . import autotune
-                options = autotune.cached_options(N, K, self.J, int(om.shape[0]), autotune.SHIPPED_CACHE, self.device)
+                options = autotune.cached_options(N, K, self.J, int(om.shape[0]), autotune.SHIPPED_CACHE, self.device,
+                                                  C)
             opt = options_struct(options) if options else None
             keep += [om, coils, opt]
             desc = descs[i]

@@ -176,9 +176,9 @@ def test_nonfinite_trajectory_rejected(dev):
 
 @pytest.mark.parametrize("opts", [dict(interp_merge=-1), dict(fuse_reduce=3), dict(presort=3), dict(grid_chunk=32),
                                   dict(fft_groups=-1), dict(grid_mfma=4), dict(interpolator=2),
-                                  dict(weight_table=2)],
+                                  dict(weight_table=2), dict(fft_radix=4)],
                          ids=["interp_merge", "fuse_reduce", "presort", "grid_chunk", "fft_groups", "grid_mfma",
-                              "interpolator", "weight_table"])
+                              "interpolator", "weight_table", "fft_radix"])
 def test_out_of_range_options_rejected(dev, opts):
     """Every tuning knob outside its documented range is an argument error."""
     from paper_1710_03197_amd import NufftError, Plan
@@ -330,6 +330,12 @@ OPTION_CASES = [
     ((16, 16, 16), dict(tile=(8, 8, 16), grid_mfma=3, weight_table=1)),
     ((4, 4, 8), dict(tile=(8, 8, 16), weight_table=1)),
     ((64,), dict(tile=(16,), weight_table=1)),
+    ((96, 80), dict(fft_radix=1)),                               # radix schedules, K = 192 x 160
+    ((96, 80), dict(fft_radix=2)),
+    ((96, 80), dict(fft_radix=3)),
+    ((64, 64), dict(fft_radix=1, tile=(16, 16))),
+    ((16, 16, 16), dict(fft_radix=3, tile=(8, 8, 16))),
+    ((120,), dict(fft_radix=2, tile=(16,))),
     ((16, 16, 16), dict(tile=(8, 8, 8), interp_merge=3)),
     ((64,), dict(tile=(16,), interp_merge=5)),
 ]

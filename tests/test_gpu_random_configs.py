@@ -54,8 +54,12 @@ def _case(seed):
             opts[key] = v
     # the window table, drawn from a stream of its own (the draws above keep
     # their configurations)
-    if np.random.default_rng(1000 + seed).random() < 0.5:
+    extra = np.random.default_rng(1000 + seed)
+    if extra.random() < 0.5:
         opts["weight_table"] = 1
+    radix = int(extra.integers(0, 4))
+    if radix:
+        opts["fft_radix"] = radix
     return N, K, J, om.astype(np.float32), opts
 
 
