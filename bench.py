@@ -39,17 +39,24 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "NUFFT fwd+adj pairs/s, 2D 256² & 3D 128³ at rel err≤1e-5; batched vs looped"
 TOL = 1e-5
 
-# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
-# this benchmark (KiB per dispatch), each scaled by what the counter reports for
-# a 256 MiB device-to-device copy (reads: x2.000, writes: x1.000); see
-# profiles/traffic_2d_256_radial.md.  An entry applies only while kernels.hip
+# HBM traffic per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# of this benchmark: read bytes = 128 TCC_EA0_RDREQ_128B + 64 TCC_EA0_RDREQ_64B
+# + 32 TCC_EA0_RDREQ_32B, write bytes = 64 TCC_EA0_WRREQ_64B + 32 (the rest of
+# TCC_EA0_WRREQ); the 1 GiB device copy this benchmark times reads and writes
+# exactly its size by the same formulas (profiles/traffic_2d_256_radial.md,
+# profiles/traffic_3d_128_koosh.md).  An entry applies only while kernels.hip
 # has the recorded sha256 prefix and the plan uses the recorded options;
 # otherwise traffic is reported as null.
 MEASURED_TRAFFIC: dict = {
-    "k_grid": {"kernels_sha": "8a781dc32f0aa520", "workload": "2d_256_golden_radial",
-               "options": {"fft_groups": 256, "fuse_reduce": 1, "grid_chunk": 512, "presort": 2, "tile": [16, 16]},
-               "fetch_kib": 3407.5, "write_kib": 2254.0, "read_scale": 2.0, "write_scale": 1.0,
-               "bytes_per_launch": 9285771},
+    ("k_grid", "2d_256_golden_radial"): {
+        "kernels_sha": "36b1a655d5deea6f",
+        "options": {"fft_groups": 256, "grid_chunk": 512, "tile": [16, 16], "weight_table": 1},
+        "read_bytes": 18463296, "write_bytes": 2308096, "bytes_per_launch": 20771392},
+    ("k_grid", "3d_128_koosh"): {
+        "kernels_sha": "36b1a655d5deea6f",
+        "options": {"fft_groups": 2048, "fft_radix": 2, "grid_chunk": 2048, "interp_merge": 4, "presort": 2,
+                    "tile": [4, 8, 16], "weight_table": 1},
+        "read_bytes": 731175232, "write_bytes": 144613376, "bytes_per_launch": 875788608},
 }
 
 
@@ -191,9 +198,8 @@ def roofline_entry(ktimes, alg, steps_hash, workload=None, options=None):
     bytes_per_launch = alg[dom] / launches_per_pair
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
-    m = MEASURED_TRAFFIC.get(dom)
-    if (m and m.get("kernels_sha") == steps_hash and m.get("workload") == workload
-            and m.get("options") == options):
+    m = MEASURED_TRAFFIC.get((dom, workload))
+    if m and m.get("kernels_sha") == steps_hash and m.get("options") == options:
         traffic = m["bytes_per_launch"]
     return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -523,7 +529,7 @@ def main():
             "plan": r2["info"], "tuning": r2["tuned"],
             "toeplitz_normal_2d": r2["toeplitz"],
             "minmax_interpolator_2d": r2["minmax"],
-            "dispatch_floor_6_launches": dispatch_floor(dev),
+            "dispatch_floor_6_launches": dispatch_floor(dev, steps=max(20, min(2000, args.steps))),
         })
     if "3d" in parts:
         r3 = bench_3d(dev, max(5, args.steps // 10), max(2, args.warmup // 4), orc_mod, tune=args.tune)
@@ -540,7 +546,8 @@ def main():
         }
     if "batched" in parts:
         extra["batched_vs_looped"] = bench_batched(dev, max(3, args.steps // 40), 2, orc_mod)
-    extra["stream_copy"] = stream_copy(dev)
+    print("[bench] device-to-device copy bandwidth", flush=True)
+    extra["stream_copy"] = stream_copy(dev, reps=20 if args.steps >= 100 else 3)
     cpu = None
     if not args.no_cpu and r2 is not None:
         cpu = cpu_baseline(orc_mod, args.cpu_seconds)

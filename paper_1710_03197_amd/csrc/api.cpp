@@ -459,6 +459,10 @@ int bin_points(nufft_plan_s *p, const float *om_dev, hipStream_t s) {
         std::vector<GridItem> sorted(items.size());
         for (size_t q = 0; q < ord.size(); ++q) sorted[q] = items[ord[q]];
         items.swap(sorted);
+        // (Measured: keeping gather items in tile order, dealt to the XCDs in
+        // runs of neighbouring tiles, cuts the 3D gather's HBM reads by a
+        // third through L2 hits on the halos but runs slower than longest
+        // first, which balances the crowded centre over the chip.)
         std::stable_sort(iitems.begin(), iitems.end(),
                          [](const InterpItem &x, const InterpItem &y) { return x.count > y.count; });
     }
