@@ -124,6 +124,11 @@ int nufft_plan(int d, const int64_t *N, const int64_t *K, int J, int64_t M,
  *                 (Section 2.1 "Oversampled FFT"): 0: radices 8, 4, 2, 3, 5
  *                 taken greedily in that order; 1: 4, 8, 2, 3, 5; 2: 3, 5,
  *                 8, 4, 2; 3: schedule 0's passes in reverse order
+ *   grid_waves    wavefronts per work item of the gridding by 4 x 4 blocks:
+ *                 4 (the default, 0 asks for it) sum their partial tiles
+ *                 in a fixed order at the end; 1: one wavefront per item,
+ *                 which writes its tile from registers (pair it with a
+ *                 smaller grid_chunk); ignored by the other gridding kernels
  *   reserved      must be 0
  *   interp_merge  most grid tiles along the last axis that one interpolation
  *                 work item covers when their samples are few (>= 1; the
@@ -143,7 +148,8 @@ typedef struct {
     int interp_merge;
     int weight_table;
     int fft_radix;
-    int reserved[3];
+    int grid_waves;
+    int reserved[2];
 } nufft_options_t;
 
 /* nufft_plan with tuning options (opt may be NULL = defaults). */

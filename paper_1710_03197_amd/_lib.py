@@ -42,7 +42,7 @@ class PlanOptions(ctypes.Structure):
                 ("interp_direct", ctypes.c_int), ("presort", ctypes.c_int),
                 ("fuse_reduce", ctypes.c_int), ("grid_mfma", ctypes.c_int), ("interpolator", ctypes.c_int),
                 ("interp_merge", ctypes.c_int), ("weight_table", ctypes.c_int), ("fft_radix", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("grid_waves", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class ProblemDesc(ctypes.Structure):

@@ -120,9 +120,14 @@ def tune(om: torch.Tensor, N, K=None, J: int = 6, reps: int = 10, path: str | No
     tried = 0
     # 1) tile shape and gridding chunk, timed on the two sample stages
     best, best_t = {}, float("inf")
-    for tile in TILE_CANDIDATES[d]:
+    # 3D tiles that the gridding by 4 x 4 blocks takes are also tried with one
+    # wavefront per work item
+    blk = [(8, 8, 16), (16, 8, 16), (8, 16, 16)]
+    for tile, waves in [(t, 4) for t in TILE_CANDIDATES[d]] + [(t, 1) for t in TILE_CANDIDATES[d] if t in blk]:
         for chunk in CHUNK_CANDIDATES:
             opts = dict(tile=tile, grid_chunk=chunk)
+            if waves == 1:
+                opts["grid_waves"] = 1
             try:
                 p = Plan(om, N, K, J, options=opts)
             except RuntimeError:

@@ -143,6 +143,7 @@ struct nufft_plan_s {
     bool fuse_reduce = false;  // first inverse FFT pass sums the partial tiles
     bool grid_mfma = false;    // gridding on the matrix cores by row tiles
     bool grid_blk = false;     // 3D gridding on the matrix cores by 4 x 4 blocks
+    int grid_waves = 4;        // its wavefronts per work item (1 or 4)
     int rec_stride = 0;        // its LDS floats per staged sample
     int seg_len = 16, segs = 1;
     int group_lanes = 64;
@@ -808,6 +809,7 @@ int run_vh(nufft_plan_s *p, const float2 *y, int grids, float2 *h, hipStream_t s
     a.mfma = p->grid_mfma;
     a.rec_stride = p->rec_stride;
     a.blk = p->grid_blk;
+    a.grid_waves = p->grid_waves;
     {
         int tsum = 0;
         for (int ax = 0; ax < p->d; ++ax) tsum += p->T[ax];
@@ -1502,10 +1504,13 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
     if (opt && (opt->interpolator < 0 || opt->interpolator > 1))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "interpolator takes 0 (Kaiser-Bessel) or 1 (min-max)"));
     p->minmax = opt && opt->interpolator == 1;
-    if (opt && (opt->reserved[0] || opt->reserved[1] || opt->reserved[2]))
+    if (opt && (opt->reserved[0] || opt->reserved[1]))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "reserved option fields must be 0"));
     if (opt && (opt->fft_radix < 0 || opt->fft_radix > 3))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "fft_radix takes 0, 1, 2 or 3"));
+    if (opt && opt->grid_waves != 0 && opt->grid_waves != 1 && opt->grid_waves != 4)
+        return bail(fail(NUFFT_ERR_INVALID_ARG, "grid_waves takes 0, 1 or 4"));
+    p->grid_waves = (opt && opt->grid_waves == 1) ? 1 : 4;
     if (opt && (opt->weight_table < 0 || opt->weight_table > 1))
         return bail(fail(NUFFT_ERR_INVALID_ARG, "weight_table takes 0 or 1"));
     p->use_wtab = opt && opt->weight_table == 1;

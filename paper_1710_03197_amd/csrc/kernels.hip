@@ -1655,8 +1655,9 @@ __global__ __launch_bounds__(256) void k_grid_mfma_multi(const GridArgs *__restr
 // registers, running only the products of blocks that one of the four
 // reaches.  Wavefronts synchronise only with themselves until the end, where
 // their tiles are summed in wave order (the result does not depend on
-// scheduling).
-template <int NJ, int T0, int T1, bool TAB>
+// scheduling).  With NW = 1 a work item is one wavefront, which writes its
+// blocks straight from registers (no summation across wavefronts).
+template <int NJ, int T0, int T1, bool TAB, int NW>
 __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, int g) {
     constexpr int T2 = 16;
     constexpr int NB1 = T1 / 4;
@@ -1673,7 +1674,7 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
     const GridItem it = a.items[item];
     const int nseg = grid_item_segments(a, item, seg_lo, seg_pre);
     const int J = a.geo.J;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     float *rec = blk_lds + wave * 64 * (RS + 1);                 // [64][RS]
     unsigned *smask = reinterpret_cast<unsigned *>(rec + 64 * RS);  // [64]
@@ -1727,7 +1728,7 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
         }
     };
     fetch(0);
-    for (int b0 = 0; b0 < n; b0 += 256) {
+    for (int b0 = 0; b0 < n; b0 += 64 * NW) {
         {
             float4 *z = reinterpret_cast<float4 *>(rec);
             for (int e = lane; e < 16 * RS; e += 64) z[e] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1796,7 +1797,7 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
                 if ((bm[0] >> b) & 1u) mk |= bm[1] << (b * NB1);
         }
         smask[lane] = mk;
-        if (b0 + 256 < n) fetch(b0 + 256);
+        if (b0 + 64 * NW < n) fetch(b0 + 64 * NW);
         group_sync(64);
         // ---- walk: lane l < 16 looks at samples 4l .. 4l + 3 (one product's
         // worth) and the blocks they reach.  Block by block, the wavefront
@@ -1831,9 +1832,28 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
         }
         group_sync(64);
     }
-    // ---- sum the wavefronts' tiles in wave order and write the tile.  D[i][j]
-    // of block q sits in lane j + 16 (i / 4), register i % 4, block row i being
-    // (x0, x1) = (4 (q / NB1) + i / 4, 4 (q % NB1) + i % 4).
+    // ---- write the tile.  D[i][j] of block q sits in lane j + 16 (i / 4),
+    // register i % 4, block row i being (x0, x1) = (4 (q / NB1) + i / 4,
+    // 4 (q % NB1) + i % 4).
+    const bool to_partial = it.nchunks > 1;
+    float2 *dst = to_partial ? a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells
+                             : a.h + int64_t(g) * a.grid_elems;
+    const int64_t K1 = a.geo.K[1], K2 = a.geo.K[2];
+    if constexpr (NW == 1) {
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) {
+            const int x0 = 4 * (q / NB1) + kq;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x1 = 4 * (q % NB1) + r;
+                const int64_t idx = to_partial ? int64_t((x0 * T1 + x1) * T2 + rl)
+                                               : (int64_t(base[0] + x0) * K1 + base[1] + x1) * K2 + base[2] + rl;
+                dst[idx] = make_float2(acc_re[q][r], acc_im[q][r]);
+            }
+        }
+        return;
+    }
+    // several wavefronts: their tiles are summed in wave order
     __syncthreads();  // every wave is done with its staging area
     float2 *red = reinterpret_cast<float2 *>(blk_lds);  // [4][CELLS], reuses the staging LDS
 #pragma unroll
@@ -1846,30 +1866,26 @@ __device__ __forceinline__ void grid_blk_body(const GridArgs &a, int64_t item, i
         }
     }
     __syncthreads();
-    const bool to_partial = it.nchunks > 1;
-    float2 *dst = to_partial ? a.partials + (int64_t(g) * a.n_slots + it.slot + it.chunk) * a.tile_cells
-                             : a.h + int64_t(g) * a.grid_elems;
-    const int64_t K1 = a.geo.K[1], K2 = a.geo.K[2];
-    for (int e = threadIdx.x; e < CELLS; e += 256) {
+    for (int e = threadIdx.x; e < CELLS; e += 64 * NW) {
         float2 sum = red[e];
 #pragma unroll
-        for (int w = 1; w < 4; ++w) sum = cadd(sum, red[w * CELLS + e]);
+        for (int w = 1; w < NW; ++w) sum = cadd(sum, red[w * CELLS + e]);
         const int x2 = e % T2, x1 = (e / T2) % T1, x0 = e / (T1 * T2);
         const int64_t idx = to_partial ? int64_t(e) : (int64_t(base[0] + x0) * K1 + base[1] + x1) * K2 + base[2] + x2;
         dst[idx] = sum;
     }
 }
 
-template <int NJ, int T0, int T1, bool TAB>
-__global__ __launch_bounds__(256) void k_grid_blk(GridArgs a) {
-    grid_blk_body<NJ, T0, T1, TAB>(a, blockIdx.x, blockIdx.y);
+template <int NJ, int T0, int T1, bool TAB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_grid_blk(GridArgs a) {
+    grid_blk_body<NJ, T0, T1, TAB, NW>(a, blockIdx.x, blockIdx.y);
 }
 
-template <int NJ, int T0, int T1, bool TAB>
-__global__ __launch_bounds__(256) void k_grid_blk_multi(const GridArgs *__restrict__ jobs,
-                                                       const int4 *__restrict__ blocks) {
+template <int NJ, int T0, int T1, bool TAB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_grid_blk_multi(const GridArgs *__restrict__ jobs,
+                                                           const int4 *__restrict__ blocks) {
     const int4 b = blocks[blockIdx.x];
-    grid_blk_body<NJ, T0, T1, TAB>(jobs[b.x], b.y, b.z);
+    grid_blk_body<NJ, T0, T1, TAB, NW>(jobs[b.x], b.y, b.z);
 }
 
 // Sums the partial tiles of every split tile in chunk order; one workgroup per
@@ -2527,30 +2543,41 @@ hipError_t launch_grid_mfma_d(const GridArgs &a, hipStream_t s) {
     return launch_grid_mfma_j<DIM, 16>(a, s);
 }
 
+template <int NJ, int T0, int T1, bool TAB, int NW, bool MULTI>
+void launch_grid_blk_i(const GridArgs &a, const GridArgs *jobs, const int4 *blocks, int64_t nblocks, size_t lds,
+                       hipStream_t s) {
+    if (MULTI)
+        launch_kernel((k_grid_blk_multi<NJ, T0, T1, TAB, NW>), dim3(unsigned(nblocks)), dim3(64 * NW), lds, s, jobs,
+                      blocks);
+    else
+        launch_kernel((k_grid_blk<NJ, T0, T1, TAB, NW>), dim3(unsigned(a.n_items), unsigned(a.grids)), dim3(64 * NW),
+                      lds, s, a);
+}
+
+template <int NJ, int T0, int T1, bool MULTI>
+hipError_t launch_grid_blk_t(const GridArgs &a, const GridArgs *jobs, const int4 *blocks, int64_t nblocks,
+                             size_t lds, hipStream_t s) {
+    const bool tab = NJ <= 8 && use_table(a.geo);
+    if (a.grid_waves == 1) {
+        if (tab)
+            launch_grid_blk_i<NJ, T0, T1, true, 1, MULTI>(a, jobs, blocks, nblocks, lds, s);
+        else
+            launch_grid_blk_i<NJ, T0, T1, false, 1, MULTI>(a, jobs, blocks, nblocks, lds, s);
+    } else {
+        if (tab)
+            launch_grid_blk_i<NJ, T0, T1, true, 4, MULTI>(a, jobs, blocks, nblocks, lds, s);
+        else
+            launch_grid_blk_i<NJ, T0, T1, false, 4, MULTI>(a, jobs, blocks, nblocks, lds, s);
+    }
+    return hipGetLastError();
+}
+
 template <int NJ, bool MULTI>
 hipError_t launch_grid_blk_j(const GridArgs &a, const GridArgs *jobs, const int4 *blocks, int64_t nblocks,
                              size_t lds, hipStream_t s) {
-#define NUFFT_BLK_CASE(T0, T1)                                                                                 \
-    if (a.T[0] == T0 && a.T[1] == T1) {                                                                        \
-        if (MULTI && tab)                                                                                      \
-            launch_kernel((k_grid_blk_multi<NJ, T0, T1, true>), dim3(unsigned(nblocks)), dim3(256), lds, s,    \
-                          jobs, blocks);                                                                       \
-        else if (MULTI)                                                                                        \
-            launch_kernel((k_grid_blk_multi<NJ, T0, T1, false>), dim3(unsigned(nblocks)), dim3(256), lds, s,   \
-                          jobs, blocks);                                                                       \
-        else if (tab)                                                                                          \
-            launch_kernel((k_grid_blk<NJ, T0, T1, true>), dim3(unsigned(a.n_items), unsigned(a.grids)),        \
-                          dim3(256), lds, s, a);                                                               \
-        else                                                                                                   \
-            launch_kernel((k_grid_blk<NJ, T0, T1, false>), dim3(unsigned(a.n_items), unsigned(a.grids)),       \
-                          dim3(256), lds, s, a);                                                               \
-        return hipGetLastError();                                                                              \
-    }
-    const bool tab = NJ <= 8 && use_table(a.geo);
-    NUFFT_BLK_CASE(8, 8)
-    NUFFT_BLK_CASE(8, 16)
-    NUFFT_BLK_CASE(16, 8)
-#undef NUFFT_BLK_CASE
+    if (a.T[0] == 8 && a.T[1] == 8) return launch_grid_blk_t<NJ, 8, 8, MULTI>(a, jobs, blocks, nblocks, lds, s);
+    if (a.T[0] == 8 && a.T[1] == 16) return launch_grid_blk_t<NJ, 8, 16, MULTI>(a, jobs, blocks, nblocks, lds, s);
+    if (a.T[0] == 16 && a.T[1] == 8) return launch_grid_blk_t<NJ, 16, 8, MULTI>(a, jobs, blocks, nblocks, lds, s);
     return hipErrorInvalidValue;
 }
 
@@ -2590,7 +2617,8 @@ int grid_variant(const GridArgs &a) {
             a.T[0] * a.T[1] > 128)
             return -1;
         const int nj = a.geo.J <= 6 ? 0 : a.geo.J <= 8 ? 1 : 2;
-        return 3000 + 10 * nj + (a.T[0] == 16 ? 2 : 0) + (a.T[1] == 16 ? 1 : 0);
+        if (a.grid_waves != 1 && a.grid_waves != 4) return -1;
+        return 3000 + 100 * a.grid_waves + 10 * nj + (a.T[0] == 16 ? 2 : 0) + (a.T[1] == 16 ? 1 : 0);
     }
     if (a.mfma) {
         if (a.geo.d < 2 || a.T[a.geo.d - 1] != 16) return -1;
@@ -2607,9 +2635,10 @@ int grid_variant(const GridArgs &a) {
 }
 
 size_t grid_lds(const GridArgs &a) {
-    if (a.blk)
-        return std::max(size_t(256) * (3 + a.T[0] + a.T[1] + a.T[2] + 1) * sizeof(float),
-                        size_t(4) * a.tile_cells * sizeof(float2));
+    if (a.blk) {
+        const size_t staged = size_t(64) * a.grid_waves * (3 + a.T[0] + a.T[1] + a.T[2] + 1) * sizeof(float);
+        return a.grid_waves == 1 ? staged : std::max(staged, size_t(a.grid_waves) * a.tile_cells * sizeof(float2));
+    }
     if (a.mfma) {
         int tsum = 0;
         for (int ax = 0; ax < a.geo.d; ++ax) tsum += a.T[ax];

@@ -248,6 +248,7 @@ struct GridArgs {
     int rec_stride;       // its LDS floats per staged sample: 2 + sum of T_a, made odd
     int blk;              // 3D matrix-core gridding by 4 x 4 blocks (T_2 = 16, T_0 and T_1 in {8, 16})
     int grids_per_wg;     // row-tile matrix-core gridding: grids one workgroup grids together (1, 2, 4)
+    int grid_waves;       // block gridding: wavefronts per work item (1 or 4)
 };
 // Grids per workgroup of the row-tile matrix-core gridding: the window weights
 // are staged once for all of them (coils and batch entries share the

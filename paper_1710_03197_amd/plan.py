@@ -51,6 +51,7 @@ def options_struct(options: dict | None) -> "_lib.PlanOptions":
     opt.interp_merge = int(options.get("interp_merge", 0))
     opt.weight_table = int(options.get("weight_table", 0))
     opt.fft_radix = int(options.get("fft_radix", 0))
+    opt.grid_waves = int(options.get("grid_waves", 0))
     interp = options.get("interpolator", 0)
     opt.interpolator = {"kb": 0, "kaiser-bessel": 0, "minmax": 1, "min-max": 1}.get(interp, interp) \
         if isinstance(interp, str) else int(interp)

@@ -176,9 +176,9 @@ def test_nonfinite_trajectory_rejected(dev):
 
 @pytest.mark.parametrize("opts", [dict(interp_merge=-1), dict(fuse_reduce=3), dict(presort=3), dict(grid_chunk=32),
                                   dict(fft_groups=-1), dict(grid_mfma=4), dict(interpolator=2),
-                                  dict(weight_table=2), dict(fft_radix=4)],
+                                  dict(weight_table=2), dict(fft_radix=4), dict(grid_waves=2)],
                          ids=["interp_merge", "fuse_reduce", "presort", "grid_chunk", "fft_groups", "grid_mfma",
-                              "interpolator", "weight_table", "fft_radix"])
+                              "interpolator", "weight_table", "fft_radix", "grid_waves"])
 def test_out_of_range_options_rejected(dev, opts):
     """Every tuning knob outside its documented range is an argument error."""
     from paper_1710_03197_amd import NufftError, Plan
@@ -338,6 +338,11 @@ OPTION_CASES = [
     ((120,), dict(fft_radix=2, tile=(16,))),
     ((16, 16, 16), dict(tile=(8, 8, 8), interp_merge=3)),
     ((64,), dict(tile=(16,), interp_merge=5)),
+    ((16, 16, 16), dict(tile=(8, 8, 16), grid_waves=1)),            # block gridding, one wavefront per item
+    ((32, 32, 32), dict(tile=(16, 8, 16), grid_waves=1, grid_chunk=64, presort=2)),
+    ((32, 32, 32), dict(tile=(8, 16, 16), grid_waves=1, weight_table=1, fuse_reduce=1)),
+    ((4, 4, 8), dict(tile=(8, 8, 16), grid_waves=1)),               # wrapped windows
+    ((16, 16, 16), dict(tile=(8, 8, 16), grid_waves=1, grid_mfma=2)),  # ignored off the block kernel
 ]
 
 

@@ -60,6 +60,8 @@ def _case(seed):
     radix = int(extra.integers(0, 4))
     if radix:
         opts["fft_radix"] = radix
+    if extra.random() < 0.5:
+        opts["grid_waves"] = 1
     return N, K, J, om.astype(np.float32), opts
 
 
