@@ -1594,9 +1594,7 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         p->grid_mfma = !p->grid_blk && mfma_ok && !(opt && opt->grid_mfma == 2);
     }
     {
-        int64_t lead = sizeof(float2);
-        for (int a = 0; a < d - 1; ++a) lead *= p->T[a] + J - 1;
-        const int64_t region = lead * (p->T[d - 1] + J - 1);
+        const int64_t region = interp_region_elems(d, p->T, J, 1) * int64_t(sizeof(float2));
         p->staged_interp = region <= kLdsBudget && !(opt && opt->interp_direct);
         // Runs of sparse tiles per gather item: measured, longer items cost
         // the latency-bound 2D workload more than the staging they save, the
@@ -1604,7 +1602,7 @@ int nufft_plan_ex(int d, const int64_t *N, const int64_t *K, int J, int64_t M, c
         const int want = (opt && opt->interp_merge > 0) ? opt->interp_merge : (d == 3 ? 2 : 1);
         p->interp_merge = 1;
         while (p->interp_merge < std::min(want, p->nt[d - 1]) &&
-               lead * ((p->interp_merge + 1) * p->T[d - 1] + J - 1) <= kInterpLdsBudget)
+               interp_region_elems(d, p->T, J, p->interp_merge + 1) * int64_t(sizeof(float2)) <= kInterpLdsBudget)
             ++p->interp_merge;
     }
     if ((p->nbins << d) >= (int64_t(1) << 30)) return bail(fail(NUFFT_ERR_UNSUPPORTED, "too many bins"));

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "nufft_internal.h"
 
@@ -921,14 +922,19 @@ __device__ __forceinline__ void interp_body(const InterpArgs &a, int64_t item) {
             t /= a.nt[ax];
         }
     }
-    int region = 1;
+    // region: rows over the leading axes, each of P elements along the last
+    // axis (its extent E made odd: the rows the lanes read then start in
+    // different LDS banks)
+    int rows = 1;
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) {
         base[ax] = tc[ax] * a.T[ax];
         // a run of it.tiles tiles along the last axis, plus the J - 1 halo
         E[ax] = (ax == DIM - 1 ? it.tiles : 1) * a.T[ax] + J - 1;
-        region *= E[ax];
+        if (ax < DIM - 1) rows *= E[ax];
     }
+    const int P = E[DIM - 1] | 1;
+    const int region = rows * P;
     constexpr int SPT = kInterpSamplesPerThread;
     float w[SPT][DIM][J];
     int off[SPT];
@@ -957,7 +963,7 @@ __device__ __forceinline__ void interp_body(const InterpArgs &a, int64_t item) {
                 for (int ax = 0; ax < DIM; ++ax) {
 #pragma unroll
                     for (int j = 0; j < J; ++j) w[k][ax][j] = wt[ax][j];
-                    o = o * E[ax] + (kw[ax] - base[ax]);
+                    o = o * (ax == DIM - 1 ? P : E[ax]) + (kw[ax] - base[ax]);
                 }
             } else {
 #pragma unroll
@@ -966,49 +972,109 @@ __device__ __forceinline__ void interp_body(const InterpArgs &a, int64_t item) {
                     const float f = window_pos<J>(a.geo, ax, a.om_sorted[i * DIM + ax], kk);
                     window_weights<J>(a.geo, a.geo.coef[ax], a.geo.nq[ax], f, w[k][ax]);
                     if (a.geo.minmax) mm_sign_taps<J>(w[k][ax], mm_wrap_from(a.geo, ax, a.om_sorted[i * DIM + ax]));
-                    o = o * E[ax] + (kk[0] - base[ax]);
+                    o = o * (ax == DIM - 1 ? P : E[ax]) + (kk[0] - base[ax]);
                 }
             }
             off[k] = o;
             if (a.geo.minmax) ph[k] = mm_phase<DIM>(a.geo, a.om_sorted + i * DIM);
         }
     }
-    // grid index of region element e (tile + halo, wrapped at the grid's edge)
-    FastDiv byE[DIM];
-#pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) byE[ax] = FastDiv(E[ax]);
-    auto grid_index = [&](int e) {
-        int l[DIM];
-#pragma unroll
-        for (int ax = DIM - 1; ax > 0; --ax) {
-            const int q = byE[ax].div(e);
-            l[ax] = byE[ax].rem(e, q);
-            e = q;
+    // grid index of the first element of region row r (leading axes wrapped
+    // at the grid's edge; the last axis is added by the caller)
+    FastDiv byE1(DIM == 3 ? E[1] : 1);
+    auto row_index = [&](int r) -> int64_t {
+        if constexpr (DIM == 1) {
+            return 0;
+        } else if constexpr (DIM == 2) {
+            int k0 = base[0] + r;
+            if (k0 >= a.geo.K[0]) k0 -= a.geo.K[0];
+            return int64_t(k0) * a.geo.K[1];
+        } else {
+            const int l0 = byE1.div(r);
+            int k0 = base[0] + l0, k1 = base[1] + byE1.rem(r, l0);
+            if (k0 >= a.geo.K[0]) k0 -= a.geo.K[0];
+            if (k1 >= a.geo.K[1]) k1 -= a.geo.K[1];
+            return (int64_t(k0) * a.geo.K[1] + k1) * a.geo.K[2];
         }
-        l[0] = e;
-        int64_t idx = 0;
-#pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) {
-            int k = base[ax] + l[ax];
-            if (k >= a.geo.K[ax]) k -= a.geo.K[ax];
-            idx = idx * a.geo.K[ax] + k;
-        }
-        return idx;
     };
+    const int KL = a.geo.K[DIM - 1];
+    const int H = (E[DIM - 1] + 1) >> 1;  // element pairs that cover a region row
+    // pairs of the last axis in one 16-byte load: the grid's rows and the
+    // region's first column must be even and the grid 16-byte aligned (a pair
+    // then never straddles the wrap, K_last being even)
+    const bool paired = (KL % 2 == 0) && (a.T[DIM - 1] % 2 == 0) && (a.grid_elems % 2 == 0) &&
+                        (reinterpret_cast<uintptr_t>(a.G) % 16 == 0);
+    // this thread's place in the row-major walk over the region's pairs: the
+    // column stays fixed, the row advances by RP per round
+    const int RP = H <= 256 ? 256 / H : 1;
+    const int pr0 = H <= 256 ? int(threadIdx.x) / H : 0;
+    const int pc = H <= 256 ? int(threadIdx.x) - pr0 * H : int(threadIdx.x);
+    int kl = base[DIM - 1] + 2 * pc;  // grid column of the pair (< 2 K_last)
+    if (kl >= KL) kl -= KL;
     for (int g = 0; g < a.grids; ++g) {
         const float2 *G = a.G + int64_t(g) * a.grid_elems;
         __syncthreads();
-        // stage the region, eight elements per thread in flight at a time
-        // (indices clamped into the region, so every load is in bounds)
-        constexpr int U = 8;
-        for (int e0 = 0; e0 < region; e0 += U * 256) {
-            float2 v[U];
+        constexpr int U = 8;  // loads in flight per thread
+        if (paired && H <= 256) {
+            // (2D regions are a few rows: 2 paired loads keep the registers,
+            // and the occupancy, of the element path)
+            constexpr int UP = DIM == 3 ? U : 2;
+            // rows of the region, H lanes per row, RP rows per round: the
+            // NR rounds go in batches of up to U whose loads are issued
+            // together (rows past the region clamped to its last row, so
+            // every load is in bounds, and not stored); idle lanes
+            // (pr0 >= RP) skip
+            const float4 *G4 = reinterpret_cast<const float4 *>(G);
+            auto rows_batch = [&](int u0, auto nu) {
+                constexpr int NU = decltype(nu)::value;
+                float4 v[NU];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = G[grid_index(min(e0 + u * 256 + int(threadIdx.x), region - 1))];
+                for (int u = 0; u < NU; ++u)
+                    v[u] = G4[(row_index(min(pr0 + (u0 + u) * RP, rows - 1)) + kl) >> 1];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * 256 + threadIdx.x;
-                if (e < region) reg[e] = v[u];
+                for (int u = 0; u < NU; ++u) {
+                    const int r = pr0 + (u0 + u) * RP;
+                    if (r < rows) {
+                        float2 *dst = reg + r * P + 2 * pc;
+                        dst[0] = make_float2(v[u].x, v[u].y);
+                        if (2 * pc + 1 < P) dst[1] = make_float2(v[u].z, v[u].w);
+                    }
+                }
+            };
+            if (pr0 < RP) {
+                const int NR = (rows + RP - 1) / RP;
+                for (int u0 = 0; u0 < NR; u0 += UP) {
+                    switch (min(UP, NR - u0)) {
+                        case 1: rows_batch(u0, std::integral_constant<int, 1>()); break;
+                        case 2: rows_batch(u0, std::integral_constant<int, 2>()); break;
+                        case 3: rows_batch(u0, std::integral_constant<int, 3>()); break;
+                        case 4: rows_batch(u0, std::integral_constant<int, 4>()); break;
+                        case 5: rows_batch(u0, std::integral_constant<int, 5 <= UP ? 5 : 1>()); break;
+                        case 6: rows_batch(u0, std::integral_constant<int, 6 <= UP ? 6 : 1>()); break;
+                        case 7: rows_batch(u0, std::integral_constant<int, 7 <= UP ? 7 : 1>()); break;
+                        default: rows_batch(u0, std::integral_constant<int, UP>()); break;
+                    }
+                }
+            }
+        } else {
+            // element by element (odd tiles, unaligned grids, rows longer
+            // than 512 elements), U elements per thread in flight
+            FastDiv byP(P);
+            for (int e0 = 0; e0 < region; e0 += U * 256) {
+                float2 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = min(e0 + u * 256 + int(threadIdx.x), region - 1);
+                    const int r = byP.div(e);
+                    int k = base[DIM - 1] + byP.rem(e, r);
+                    if (k >= KL) k -= KL;
+                    v[u] = G[row_index(r) + k];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * 256 + threadIdx.x;
+                    if (e < region) reg[e] = v[u];
+                }
             }
         }
         __syncthreads();
@@ -1023,7 +1089,7 @@ __device__ __forceinline__ void interp_body(const InterpArgs &a, int64_t item) {
             } else if constexpr (DIM == 2) {
 #pragma unroll
                 for (int j0 = 0; j0 < J; ++j0) {
-                    const float2 *row = r0 + j0 * E[1];
+                    const float2 *row = r0 + j0 * P;
                     float2 rs = make_float2(0.f, 0.f);
 #pragma unroll
                     for (int j1 = 0; j1 < J; ++j1) rs = cadd(rs, cscale(row[j1], w[k][1][j1]));
@@ -1034,7 +1100,7 @@ __device__ __forceinline__ void interp_body(const InterpArgs &a, int64_t item) {
                     float2 ps = make_float2(0.f, 0.f);
 #pragma unroll
                     for (int j1 = 0; j1 < J; ++j1) {
-                        const float2 *row = r0 + (j0 * E[1] + j1) * E[2];
+                        const float2 *row = r0 + (j0 * E[1] + j1) * P;
                         float2 rs = make_float2(0.f, 0.f);
 #pragma unroll
                         for (int j2 = 0; j2 < J; ++j2) rs = cadd(rs, cscale(row[j2], w[k][2][j2]));
@@ -2455,10 +2521,7 @@ hipError_t launch_last_pass_multi(const LastJob *jobs, const int4 *blocks, int64
 
 size_t interp_lds(const InterpArgs &a) {
     if (!a.items) return 0;
-    size_t region = sizeof(float2);
-    for (int ax = 0; ax < a.geo.d; ++ax)
-        region *= size_t((ax == a.geo.d - 1 ? a.merge : 1) * a.T[ax] + a.geo.J - 1);
-    return region;
+    return size_t(interp_region_elems(a.geo.d, a.T, a.geo.J, a.merge)) * sizeof(float2);
 }
 
 hipError_t launch_interp(const InterpArgs &a, hipStream_t s) {

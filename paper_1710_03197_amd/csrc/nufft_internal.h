@@ -200,6 +200,13 @@ struct InterpArgs {
     int merge;  // most tiles one item covers (sizes the LDS region)
 };
 hipError_t launch_interp(const InterpArgs &a, hipStream_t s);
+// Elements of a gather item's LDS region: the tiles (merge of them along the
+// last axis) plus the J - 1 halo, the last axis made odd.
+inline int64_t interp_region_elems(int d, const int *T, int J, int merge) {
+    int64_t n = 1;
+    for (int ax = 0; ax < d - 1; ++ax) n *= T[ax] + J - 1;
+    return n * ((int64_t(merge) * T[d - 1] + J - 1) | 1);
+}
 
 // Gridding V^H, output driven: one work item per (tile, chunk); tiles that
 // need more than one chunk write partial tiles that reduce_partials sums.
