@@ -976,7 +976,7 @@ void stage_blocks(const Emitted &em, int job, int threads, std::vector<int4> &ou
         }
         case kStReduce: {
             const ReduceArgs &a = em.reduce;
-            const int cbs = (a.tile_cells + 255) / 256;
+            const int cbs = (a.tile_cells + kReduceCellsPerWg - 1) / kReduceCellsPerWg;
             for (int g = 0; g < a.grids; ++g)
                 for (int cb = 0; cb < cbs; ++cb)
                     for (int64_t h = 0; h < a.n_hot; ++h) out.push_back(make_int4(job, int(h), cb, g));

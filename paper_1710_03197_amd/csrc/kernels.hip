@@ -1955,10 +1955,10 @@ __global__ __launch_bounds__(64 * NW) void k_grid_blk_multi(const GridArgs *__re
 }
 
 // Sums the partial tiles of every split tile in chunk order; one workgroup per
-// (tile, 256 cells, grid).
+// (tile, kReduceCellsPerWg cells, grid), one cell per thread.
 __device__ __forceinline__ void reduce_partials_body(const ReduceArgs &a, int64_t hot, int cb, int g) {
     const HotTile ht = a.hot[hot];
-    const int e = cb * 256 + threadIdx.x;
+    const int e = cb * kReduceCellsPerWg + threadIdx.x;
     if (e >= a.tile_cells) return;
     int tc[kMaxDim];
     {
@@ -1970,14 +1970,14 @@ __device__ __forceinline__ void reduce_partials_body(const ReduceArgs &a, int64_
     }
     const float2 *p = a.partials + (int64_t(g) * a.n_slots + ht.slot) * a.tile_cells + e;
     float2 acc = make_float2(0.f, 0.f);
-    // eight partial tiles in flight per round trip, added in chunk order
-    for (int c0 = 0; c0 < ht.nchunks; c0 += 8) {
-        float2 t[8];
+    constexpr int R = 8;  // partial tiles in flight per round trip, added in chunk order
+    for (int c0 = 0; c0 < ht.nchunks; c0 += R) {
+        float2 t[R];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < R; ++j)
             if (c0 + j < ht.nchunks) t[j] = p[int64_t(c0 + j) * a.tile_cells];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < R; ++j)
             if (c0 + j < ht.nchunks) acc = cadd(acc, t[j]);
     }
     int rem = e;
@@ -2815,8 +2815,10 @@ hipError_t launch_permute_samples_multi(const PermuteJob *jobs, const int4 *bloc
 
 hipError_t launch_reduce_partials(const ReduceArgs &a, hipStream_t s) {
     if (a.n_hot == 0) return hipSuccess;
-    launch_kernel(k_reduce_partials, dim3(unsigned(a.n_hot), unsigned((a.tile_cells + 255) / 256), unsigned(a.grids)),
-                       dim3(256), 0, s, a);
+    launch_kernel(k_reduce_partials,
+                  dim3(unsigned(a.n_hot), unsigned((a.tile_cells + kReduceCellsPerWg - 1) / kReduceCellsPerWg),
+                       unsigned(a.grids)),
+                  dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -368,6 +368,7 @@ struct ReduceArgs {
     int grids;
 };
 hipError_t launch_reduce_partials(const ReduceArgs &a, hipStream_t s);
+constexpr int kReduceCellsPerWg = 256;  // tile cells one reduction workgroup sums (one per thread)
 
 // Trajectory gradient: gom[perm[i]][a] = sum_g Re(conj(gy[g][perm[i]]) * dy/domega_a).
 struct GradArgs {

@@ -343,6 +343,8 @@ OPTION_CASES = [
     ((32, 32, 32), dict(tile=(8, 16, 16), grid_waves=1, weight_table=1, fuse_reduce=1)),
     ((4, 4, 8), dict(tile=(8, 8, 16), grid_waves=1)),               # wrapped windows
     ((16, 16, 16), dict(tile=(8, 8, 16), grid_waves=1, grid_mfma=2)),  # ignored off the block kernel
+    ((96, 80), dict(tile=(16, 10), grid_chunk=64)),               # split tiles summed cell by cell (rows of 10)
+    ((96, 80), dict(tile=(16, 10), grid_chunk=64, interp_merge=3)),
 ]
 
 
