@@ -532,17 +532,23 @@ __device__ __forceinline__ void strided_pass_body(const StridedPassArgs &a, int 
             const int n = sp[u].y;
             if (n > 0) {
                 const float2 *pp = a.partials + (g * a.n_slots + sp[u].x) * a.tile_cells + cellv[u];
-                float2 acc = make_float2(0.f, 0.f);
-                for (int k0 = 0; k0 < n; k0 += 4) {
-                    float2 t[4];
+                // kReduceLanes interleaved sums (chunk c into sum c mod
+                // kReduceLanes, in chunk order), then added in lane order
+                float2 acc[kReduceLanes];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < kReduceLanes; ++j) acc[j] = make_float2(0.f, 0.f);
+                for (int k0 = 0; k0 < n; k0 += kReduceLanes) {
+                    float2 t[kReduceLanes];
+#pragma unroll
+                    for (int j = 0; j < kReduceLanes; ++j)
                         if (k0 + j < n) t[j] = pp[int64_t(k0 + j) * a.tile_cells];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (k0 + j < n) acc = cadd(acc, t[j]);
+                    for (int j = 0; j < kReduceLanes; ++j)
+                        if (k0 + j < n) acc[j] = cadd(acc[j], t[j]);
                 }
-                v[u] = acc;
+#pragma unroll
+                for (int j = 1; j < kReduceLanes; ++j) acc[0] = cadd(acc[0], acc[j]);
+                v[u] = acc[0];
             }
         }
     }
@@ -1954,12 +1960,37 @@ __global__ __launch_bounds__(64 * NW) void k_grid_blk_multi(const GridArgs *__re
     grid_blk_body<NJ, T0, T1, TAB, NW>(jobs[b.x], b.y, b.z);
 }
 
-// Sums the partial tiles of every split tile in chunk order; one workgroup per
-// (tile, kReduceCellsPerWg cells, grid), one cell per thread.
+// Sums the partial tiles of every split tile; one workgroup per (tile,
+// kReduceCellsPerWg cells, grid).  The kReduceLanes threads of a cell each
+// sum every kReduceLanes-th partial tile in chunk order, and their sums are
+// added in lane order (the order of the first inverse FFT pass that sums
+// them itself), so the dependent chain of loads of the most crowded tiles is
+// kReduceLanes times shorter.
 __device__ __forceinline__ void reduce_partials_body(const ReduceArgs &a, int64_t hot, int cb, int g) {
+    __shared__ float2 lane_sum[kReduceLanes][kReduceCellsPerWg];
     const HotTile ht = a.hot[hot];
-    const int e = cb * kReduceCellsPerWg + threadIdx.x;
-    if (e >= a.tile_cells) return;
+    const int cl = int(threadIdx.x) % kReduceCellsPerWg;  // cell of the block
+    const int ln = int(threadIdx.x) / kReduceCellsPerWg;  // its lane
+    const int e = cb * kReduceCellsPerWg + cl;
+    float2 acc = make_float2(0.f, 0.f);
+    if (e < a.tile_cells) {
+        const float2 *p = a.partials + (int64_t(g) * a.n_slots + ht.slot) * a.tile_cells + e;
+        constexpr int R = 8;  // partial tiles in flight per round trip
+        for (int c0 = ln; c0 < ht.nchunks; c0 += R * kReduceLanes) {
+            float2 t[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (c0 + j * kReduceLanes < ht.nchunks) t[j] = p[int64_t(c0 + j * kReduceLanes) * a.tile_cells];
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (c0 + j * kReduceLanes < ht.nchunks) acc = cadd(acc, t[j]);
+        }
+    }
+    lane_sum[ln][cl] = acc;
+    __syncthreads();
+    if (ln != 0 || e >= a.tile_cells) return;
+#pragma unroll
+    for (int j = 1; j < kReduceLanes; ++j) acc = cadd(acc, lane_sum[j][cl]);
     int tc[kMaxDim];
     {
         int t = ht.tile;
@@ -1967,18 +1998,6 @@ __device__ __forceinline__ void reduce_partials_body(const ReduceArgs &a, int64_
             tc[ax] = t % a.nt[ax];
             t /= a.nt[ax];
         }
-    }
-    const float2 *p = a.partials + (int64_t(g) * a.n_slots + ht.slot) * a.tile_cells + e;
-    float2 acc = make_float2(0.f, 0.f);
-    constexpr int R = 8;  // partial tiles in flight per round trip, added in chunk order
-    for (int c0 = 0; c0 < ht.nchunks; c0 += R) {
-        float2 t[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-            if (c0 + j < ht.nchunks) t[j] = p[int64_t(c0 + j) * a.tile_cells];
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-            if (c0 + j < ht.nchunks) acc = cadd(acc, t[j]);
     }
     int rem = e;
     int l[kMaxDim];

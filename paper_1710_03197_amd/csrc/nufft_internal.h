@@ -368,7 +368,10 @@ struct ReduceArgs {
     int grids;
 };
 hipError_t launch_reduce_partials(const ReduceArgs &a, hipStream_t s);
-constexpr int kReduceCellsPerWg = 256;  // tile cells one reduction workgroup sums (one per thread)
+// Split-tile reduction: tile cells per workgroup, and threads (interleaved
+// partial sums, added in lane order) per cell: 256 threads.
+constexpr int kReduceCellsPerWg = 64;
+constexpr int kReduceLanes = 4;
 
 // Trajectory gradient: gom[perm[i]][a] = sum_g Re(conj(gy[g][perm[i]]) * dy/domega_a).
 struct GradArgs {
