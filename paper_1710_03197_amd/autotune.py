@@ -35,7 +35,7 @@ TILE_CANDIDATES = {
     2: [(32, 16), (64, 16), (16, 16), (32, 32), (16, 32), (64, 8)],
     3: [(8, 8, 16), (16, 8, 16), (8, 16, 16), (8, 8, 8), (4, 8, 16), (4, 4, 16), (16, 8, 8)],
 }
-CHUNK_CANDIDATES = [256, 512, 1024, 2048]
+CHUNK_CANDIDATES = [256, 512, 1024, 1536, 2048]
 FFT_GROUP_CANDIDATES = [256, 512, 1024, 2048, 4096]
 RADIX_CANDIDATES = [1, 2, 3]  # fft_radix schedules besides the default 0
 
