@@ -49,11 +49,11 @@ TOL = 1e-5
 # otherwise traffic is reported as null.
 MEASURED_TRAFFIC: dict = {
     ("k_grid", "2d_256_golden_radial"): {
-        "kernels_sha": "7384e2984821c441",
+        "kernels_sha": "40e87707b14d1007",
         "options": {"fft_groups": 512, "grid_chunk": 512, "interp_merge": 2, "tile": [16, 16], "weight_table": 1},
         "read_bytes": 18463296, "write_bytes": 2308096, "bytes_per_launch": 20771392},
     ("k_grid", "3d_128_koosh"): {
-        "kernels_sha": "7384e2984821c441",
+        "kernels_sha": "40e87707b14d1007",
         "options": {"fft_groups": 1024, "grid_chunk": 1536, "grid_waves": 1, "interp_merge": 4, "presort": 2,
                     "tile": [8, 8, 16], "weight_table": 1},
         "read_bytes": 798889184, "write_bytes": 149938176, "bytes_per_launch": 948827360},

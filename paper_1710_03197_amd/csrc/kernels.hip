@@ -12,12 +12,15 @@
 //                  (Section 2.2, multi-coil: sum_i conj(c_i) A^H y_i).
 //   k_interp       V, a gather of J^d taps per sample (Section 2.1
 //                  "Interpolation"), samples visited in grid-tile order.
-//   k_grid         V^H (gridding), output driven: a workgroup owns one grid tile,
-//                  lanes own rows of it in registers and walk the samples that
+//   k_grid_blk     V^H (gridding) in 3D on the matrix cores by 4 x 4 blocks;
+//   k_grid_mfma    by row tiles (2D and other 16-cell tiles);
+//   k_grid         on the vector ALUs (other tiles).  All output driven: a
+//                  work item owns one grid tile and walks the samples that
 //                  reach it (staged in LDS), so the tile is written once with
 //                  plain stores: no memset, no atomics, a fixed summation
 //                  order; crowded tiles are split into chunks whose partial
-//                  tiles k_reduce_partials sums in chunk order.
+//                  tiles k_reduce_partials (or the first inverse FFT pass)
+//                  sums in a fixed order.
 //   k_grad         trajectory gradient through the derivative of the kernel.
 //
 // All arithmetic is float32 with float32 accumulation; window positions are
